@@ -1,0 +1,515 @@
+/*
+ * cs_oracle.c -- FP64 CPU oracle for clustered parametric component separation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity reference for the HIP library: only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark load it.  It shares no
+ * code, header, table or helper with the library under paper_2604_08463_amd/.
+ *
+ * Plain, single-threaded, double precision, ascending pixel order, no blocking or fusion.  Each
+ * function states the passage of the paper it follows (arXiv 2604.08463):
+ *   Sec. 2.1, eq. (data_model)          d_p = A_p(beta_p) s_p + n_p
+ *   Sec. 2.1, eq. (mixing_columns)      CMB = 1; dust modified blackbody; synchrotron power law
+ *   Sec. 2.1, eq. (mle_solution)        s_hat = (A^T N^-1 A)^-1 A^T N^-1 d
+ *   Sec. 2.1, eq. (spectral_likelihood) ln L_spec = const + 1/2 sum_p b^T M^-1 b
+ *   Sec. 2.2                            beta_p = beta_k for p in patch k
+ *   Sec. 2.3                            one independent patching per spectral parameter
+ *   Sec. 3.3.1 (gradient equation)      gradient from the GLS residuals with s held fixed
+ *   App. A.1 and Alg. 1                 affine internal box [0,1], clamp to the nearest bound
+ *
+ * Readings where the paper is silent (each one also listed in the design notes):
+ *   - objective F = -2 ln L_spec with the constant dropped: F = -sum_p sum_{Q,U} b^T M^-1 b;
+ *     its gradient is -2 r^T (dA/dtheta) s_hat, i.e. minus the printed gradient of ln L_spec
+ *     scaled by 2 (the printed one is the gradient of 2 ln L_spec).
+ *   - dust and synchrotron columns are converted from Rayleigh-Jeans to CMB units with
+ *     g(nu) = (e^y - 1)^2 / (y^2 e^y), y = h nu / (k T_CMB), normalised to 1 at nu0.
+ *   - h and k take their exact SI values; bands are delta functions at their centres.
+ *   - Q and U share the spectral parameters and have independent amplitudes.
+ *   - parity unpinned: nothing (see the oracle tests for the pin of each function).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NOT_PD 1
+#define ORC_NONFINITE 2
+#define ORC_LS_FAIL 4
+#define ORC_MAXITER 8
+#define ORC_CONVERGED 16
+
+#define ORC_E_INVALID (-1)
+#define ORC_E_LABEL (-2)
+
+/* h/k in kelvin per GHz from the exact SI values of h and k */
+static const double ORC_H_OVER_K = 6.62607015e-34 / 1.380649e-23 * 1.0e9;
+
+typedef struct {
+    int32_t nfreq;
+    int32_t npix;
+    const double *freqs;       /* [F] band centres in GHz                                    */
+    double nu0_dust, nu0_sync; /* reference frequencies of the dust / synchrotron columns  */
+    double tcmb;               /* CMB temperature in K                                     */
+    const double *d;           /* [2][F][P] Q/U data, uK_CMB                               */
+    const double *ninv;        /* [2][F] (per band) or [2][F][P] (per pixel), uK^-2        */
+    int32_t ninv_per_pixel;
+    const int32_t *labels;     /* [3][P] cluster of each pixel per parameter; -1 = excluded */
+    int32_t nclusters[3];      /* K_d, K_T, K_s                                            */
+} orc_problem;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Neumaier compensated summation                                                             */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    double s, c;
+} orc_sum;
+
+static void orc_add(orc_sum *a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double orc_val(const orc_sum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Mixing-matrix columns, Sec. 2.1 eq. (mixing_columns), in CMB thermodynamic units           */
+/* ------------------------------------------------------------------------------------------ */
+
+/* RJ -> K_CMB conversion factor g(nu) = (e^y - 1)^2 / (y^2 e^y), y = h nu / (k T_CMB) */
+double orc_rj_to_cmb(double nu_ghz, double tcmb) {
+    double y = ORC_H_OVER_K * nu_ghz / tcmb;
+    double em1 = expm1(y);
+    return em1 * em1 / (y * y * exp(y));
+}
+
+/*
+ * Columns of one band for one parameter set, plus their parameter derivatives:
+ *   a_d = (nu/nu0d)^(beta_d+1) * expm1(h nu0d/kT) / expm1(h nu/kT) * g(nu)/g(nu0d)
+ *   a_s = (nu/nu0s)^beta_s * g(nu)/g(nu0s)
+ *   da_d/dbeta_d = a_d ln(nu/nu0d)
+ *   da_d/dT_d    = a_d / T_d * [x/(1-e^-x) - x0/(1-e^-x0)],  x = h nu/kT, x0 = h nu0d/kT
+ *   da_s/dbeta_s = a_s ln(nu/nu0s)
+ */
+void orc_sed(double nu, double nu0d, double nu0s, double tcmb, double beta_d, double temp_d,
+             double beta_s, double *a_d, double *a_s, double *dad_dbeta, double *dad_dtemp,
+             double *das_dbeta) {
+    double x = ORC_H_OVER_K * nu / temp_d;
+    double x0 = ORC_H_OVER_K * nu0d / temp_d;
+    double ad = pow(nu / nu0d, beta_d + 1.0) * expm1(x0) / expm1(x) * orc_rj_to_cmb(nu, tcmb) /
+                orc_rj_to_cmb(nu0d, tcmb);
+    double as = pow(nu / nu0s, beta_s) * orc_rj_to_cmb(nu, tcmb) / orc_rj_to_cmb(nu0s, tcmb);
+    *a_d = ad;
+    *a_s = as;
+    if (dad_dbeta) *dad_dbeta = ad * log(nu / nu0d);
+    if (dad_dtemp) *dad_dtemp = ad / temp_d * (x / (-expm1(-x)) - x0 / (-expm1(-x0)));
+    if (das_dbeta) *das_dbeta = as * log(nu / nu0s);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* 3x3 solve by LU with partial pivoting (Sec. 2.1 eq. mle_solution)                          */
+/* ------------------------------------------------------------------------------------------ */
+static int orc_lu_solve3(const double m[9], const double b[3], double xout[3]) {
+    double a[3][4];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) a[i][j] = m[3 * i + j];
+        a[i][3] = b[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < 3; ++i)
+            if (fabs(a[i][k]) > fabs(a[piv][k])) piv = i;
+        if (a[piv][k] == 0.0) return 1;
+        if (piv != k)
+            for (int j = 0; j < 4; ++j) {
+                double t = a[k][j];
+                a[k][j] = a[piv][j];
+                a[piv][j] = t;
+            }
+        for (int i = k + 1; i < 3; ++i) {
+            double f = a[i][k] / a[k][k];
+            for (int j = k; j < 4; ++j) a[i][j] -= f * a[k][j];
+        }
+    }
+    for (int i = 2; i >= 0; --i) {
+        double s = a[i][3];
+        for (int j = i + 1; j < 3; ++j) s -= a[i][j] * xout[j];
+        xout[i] = s / a[i][i];
+    }
+    return 0;
+}
+
+/* positive definiteness by Sylvester's criterion: all leading principal minors > 0 */
+static int orc_is_pd3(const double m[9]) {
+    double m1 = m[0];
+    double m2 = m[0] * m[4] - m[1] * m[3];
+    double m3 = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                m[2] * (m[3] * m[7] - m[4] * m[6]);
+    return m1 > 0.0 && m2 > 0.0 && m3 > 0.0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Label checks (Sec. 2.2 / 2.3): each label in [0, K_j) or -1, and -1 on all three together  */
+/* ------------------------------------------------------------------------------------------ */
+int orc_check_labels(const orc_problem *pr) {
+    if (!pr || pr->nfreq < 1 || pr->npix < 0 || !pr->labels) return ORC_E_INVALID;
+    for (int j = 0; j < 3; ++j)
+        if (pr->nclusters[j] < 1) return ORC_E_INVALID;
+    int64_t P = pr->npix;
+    for (int64_t p = 0; p < P; ++p) {
+        int excl = 0;
+        for (int j = 0; j < 3; ++j) {
+            int32_t l = pr->labels[j * P + p];
+            if (l == -1)
+                ++excl;
+            else if (l < 0 || l >= pr->nclusters[j])
+                return ORC_E_LABEL;
+        }
+        if (excl != 0 && excl != 3) return ORC_E_LABEL;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One pixel: GLS solve, likelihood term and its gradient (Sec. 2.1, Sec. 3.3.1)             */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * Outputs (each nullable): mout[2][9] = A^T N^-1 A per Stokes, bout[2][3] = A^T N^-1 d,
+ * sout[2][3] = s_hat, rout[2][F] = N^-1 (d - A s_hat), fout = -sum_s b.s_hat,
+ * gout[3] = dfout/d(beta_d, T_d, beta_s).  Returns status bits.
+ */
+int orc_pixel(const orc_problem *pr, const double *x, int32_t p, double *mout, double *bout,
+              double *sout, double *rout, double *fout, double *gout) {
+    const int F = pr->nfreq;
+    const int64_t P = pr->npix;
+    const int32_t kd = pr->labels[p], kt = pr->labels[P + p], ks = pr->labels[2 * P + p];
+    const double beta_d = x[kd];
+    const double temp_d = x[pr->nclusters[0] + kt];
+    const double beta_s = x[pr->nclusters[0] + pr->nclusters[1] + ks];
+    int status = 0;
+    double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+
+    double *ad = (double *)malloc(sizeof(double) * 5 * (size_t)F);
+    double *as = ad + F, *dbd = ad + 2 * F, *dtd = ad + 3 * F, *dbs = ad + 4 * F;
+    for (int n = 0; n < F; ++n)
+        orc_sed(pr->freqs[n], pr->nu0_dust, pr->nu0_sync, pr->tcmb, beta_d, temp_d, beta_s, &ad[n],
+                &as[n], &dbd[n], &dtd[n], &dbs[n]);
+
+    for (int s = 0; s < 2; ++s) {
+        double m[9] = {0}, b[3] = {0}, sh[3];
+        for (int n = 0; n < F; ++n) {
+            double w = pr->ninv_per_pixel ? pr->ninv[((int64_t)s * F + n) * P + p] : pr->ninv[s * F + n];
+            double dv = pr->d[((int64_t)s * F + n) * P + p];
+            double a[3] = {1.0, ad[n], as[n]};
+            for (int i = 0; i < 3; ++i) {
+                for (int j = 0; j < 3; ++j) m[3 * i + j] += w * a[i] * a[j];
+                b[i] += w * a[i] * dv;
+            }
+        }
+        if (!orc_is_pd3(m)) status |= ORC_NOT_PD;
+        if (orc_lu_solve3(m, b, sh)) {
+            status |= ORC_NOT_PD;
+            sh[0] = sh[1] = sh[2] = NAN;
+        }
+        f -= b[0] * sh[0] + b[1] * sh[1] + b[2] * sh[2];
+        /* residual form of the gradient: dF/dtheta = -2 sum_nu r_nu (dA_nu/dtheta) s_hat */
+        for (int n = 0; n < F; ++n) {
+            double w = pr->ninv_per_pixel ? pr->ninv[((int64_t)s * F + n) * P + p] : pr->ninv[s * F + n];
+            double dv = pr->d[((int64_t)s * F + n) * P + p];
+            double r = w * (dv - (sh[0] + ad[n] * sh[1] + as[n] * sh[2]));
+            if (rout) rout[s * F + n] = r;
+            g[0] += -2.0 * r * dbd[n] * sh[1];
+            g[1] += -2.0 * r * dtd[n] * sh[1];
+            g[2] += -2.0 * r * dbs[n] * sh[2];
+        }
+        if (mout) memcpy(mout + 9 * s, m, sizeof m);
+        if (bout) memcpy(bout + 3 * s, b, sizeof b);
+        if (sout) memcpy(sout + 3 * s, sh, sizeof sh);
+    }
+    free(ad);
+    if (!isfinite(f) || !isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2])) status |= ORC_NONFINITE;
+    if (fout) *fout = f;
+    if (gout) memcpy(gout, g, sizeof g);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Whole problem: F = sum_p f_p, per-cluster gradient and per-cluster likelihood partials     */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * x, grad, cluster_f are packed [beta_d (K_d) | T_d (K_T) | beta_s (K_s)].  cluster_f[k] of
+ * labelling j is the sum of f_p over the pixels of cluster k; each labelling's partials sum to
+ * F.  Sums are Neumaier-compensated in ascending pixel order.  On a non-PD pixel F is NaN.
+ * Returns status bits (>= 0) or a negative error code.
+ */
+int orc_likelihood_grad(const orc_problem *pr, const double *x, double *neg2logl, double *grad,
+                        double *cluster_f) {
+    int rc = orc_check_labels(pr);
+    if (rc) return rc;
+    const int64_t P = pr->npix;
+    const int K = pr->nclusters[0] + pr->nclusters[1] + pr->nclusters[2];
+    const int off[3] = {0, pr->nclusters[0], pr->nclusters[0] + pr->nclusters[1]};
+    orc_sum *gs = (orc_sum *)calloc((size_t)K * 2, sizeof(orc_sum));
+    orc_sum *fs = gs + K;
+    orc_sum tot = {0.0, 0.0};
+    int status = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (pr->labels[p] < 0) continue;
+        double f, g[3];
+        status |= orc_pixel(pr, x, (int32_t)p, NULL, NULL, NULL, NULL, &f, g);
+        orc_add(&tot, f);
+        for (int j = 0; j < 3; ++j) {
+            int k = off[j] + pr->labels[j * P + p];
+            orc_add(&gs[k], g[j]);
+            orc_add(&fs[k], f);
+        }
+    }
+    if (neg2logl) *neg2logl = (status & ORC_NOT_PD) ? NAN : orc_val(&tot);
+    for (int k = 0; k < K; ++k) {
+        if (grad) grad[k] = orc_val(&gs[k]);
+        if (cluster_f) cluster_f[k] = orc_val(&fs[k]);
+    }
+    free(gs);
+    return status;
+}
+
+/* d^T N^-1 d over the included pixels (the data term of the joint chi^2, Sec. 2.1 eq. nll_joint) */
+double orc_data_chi2(const orc_problem *pr) {
+    const int F = pr->nfreq;
+    const int64_t P = pr->npix;
+    orc_sum t = {0.0, 0.0};
+    for (int64_t p = 0; p < P; ++p) {
+        if (pr->labels[p] < 0) continue;
+        for (int s = 0; s < 2; ++s)
+            for (int n = 0; n < F; ++n) {
+                double w = pr->ninv_per_pixel ? pr->ninv[((int64_t)s * F + n) * P + p] : pr->ninv[s * F + n];
+                double dv = pr->d[((int64_t)s * F + n) * P + p];
+                orc_add(&t, w * dv * dv);
+            }
+    }
+    return orc_val(&t);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Segments of one labelling: stable counting sort of pixel indices by cluster (Sec. 2.2)     */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * perm[n_incl] lists the included pixels grouped by cluster, ascending pixel index inside a
+ * cluster; offsets[K+1] is the exclusive prefix sum of the cluster sizes.  Returns n_incl, or a
+ * negative error on an out-of-range label.
+ */
+int64_t orc_segments(int64_t npix, const int32_t *labels, int32_t k, int32_t *perm, int32_t *offsets) {
+    for (int32_t c = 0; c <= k; ++c) offsets[c] = 0;
+    for (int64_t p = 0; p < npix; ++p) {
+        int32_t l = labels[p];
+        if (l == -1) continue;
+        if (l < 0 || l >= k) return ORC_E_LABEL;
+        offsets[l + 1] += 1;
+    }
+    for (int32_t c = 0; c < k; ++c) offsets[c + 1] += offsets[c];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
+    for (int32_t c = 0; c < k; ++c) fill[c] = offsets[c];
+    for (int64_t p = 0; p < npix; ++p) {
+        int32_t l = labels[p];
+        if (l < 0) continue;
+        perm[fill[l]++] = (int32_t)p;
+    }
+    free(fill);
+    return offsets[k];
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Projected L-BFGS in the internal box (App. A.1 affine map; Alg. 1 clamp-to-bound logic)    */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * Specification (shared with the device optimiser, written independently there):
+ *   y = (x - l)/(u - l) in [0,1]^K; g = dF/dx * (u - l).
+ *   free_i unless (y_i <= 0 and g_i > 0) or (y_i >= 1 and g_i < 0); Pg = g on the free set.
+ *   Direction: two-loop recursion on the free set over the stored pairs (newest first), each
+ *   pair restricted to the free set and skipped when s.t <= 1e-12 |s||t| there; H0 = gamma I
+ *   with gamma = s.t / t.t of the newest used pair (1 if none).  p = -(H Pg) on the free set;
+ *   if p.g >= 0 or p is not finite the memory is cleared and p = -Pg.
+ *   Step: alpha0 = 1, or min(1, 1/|p|_inf) when no pair was used.  Trial
+ *   y(alpha) = clip(y + alpha p, 0, 1); Armijo F(y(a)) <= F(y) + c1 g.(y(a) - y); halve alpha at
+ *   most max_backtracks times, else stop with LS_FAIL.
+ *   Accept: s = y_new - y, t = g_new - g, stored when s.t > 1e-12 |s||t| (ring of m pairs).
+ *   Stop when |Pg|_2 <= gtol |Pg_0|_2 (CONVERGED) or after max_iter iterations (MAXITER).
+ */
+typedef struct {
+    const orc_problem *pr;
+    const double *lo, *hi;
+    int K;
+    double *xphys, *gphys;
+    int64_t nevals;
+} orc_obj;
+
+static int orc_eval_internal(orc_obj *o, const double *y, double *f, double *g) {
+    for (int i = 0; i < o->K; ++i) o->xphys[i] = o->lo[i] + y[i] * (o->hi[i] - o->lo[i]);
+    int st = orc_likelihood_grad(o->pr, o->xphys, f, o->gphys, NULL);
+    o->nevals++;
+    if (st < 0) return st;
+    for (int i = 0; i < o->K; ++i) g[i] = o->gphys[i] * (o->hi[i] - o->lo[i]);
+    return st;
+}
+
+static double orc_dot_masked(const double *a, const double *b, const unsigned char *m, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (m[i]) s += a[i] * b[i];
+    return s;
+}
+
+int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double *x, int32_t m,
+              double gtol, int32_t max_iter, int32_t max_backtracks, double c1, double *fout,
+              int32_t *iters_out, int64_t *nevals_out) {
+    const int K = pr->nclusters[0] + pr->nclusters[1] + pr->nclusters[2];
+    if (m < 1 || K < 1) return ORC_E_INVALID;
+    for (int i = 0; i < K; ++i)
+        if (!(hi[i] > lo[i])) return ORC_E_INVALID;
+    double *buf = (double *)calloc((size_t)K * (8 + 2 * (size_t)m) + 2 * (size_t)m + 8, sizeof(double));
+    double *y = buf, *g = y + K, *q = g + K, *p = q + K, *yt = p + K, *gt = yt + K, *xp = gt + K,
+           *gp = xp + K, *S = gp + K, *T = S + (size_t)m * K, *alph = T + (size_t)m * K,
+           *rho = alph + m;
+    unsigned char *fr = (unsigned char *)calloc((size_t)K, 1);
+    orc_obj o = {pr, lo, hi, K, xp, gp, 0};
+    int status = 0, iters = 0, npairs = 0, newest = -1;
+    double f, ft;
+
+    for (int i = 0; i < K; ++i) {
+        double yi = (x[i] - lo[i]) / (hi[i] - lo[i]);
+        y[i] = yi < 0.0 ? 0.0 : (yi > 1.0 ? 1.0 : yi);
+    }
+    int st = orc_eval_internal(&o, y, &f, g);
+    if (st < 0) {
+        free(buf);
+        free(fr);
+        return st;
+    }
+    status |= st & (ORC_NOT_PD | ORC_NONFINITE);
+    double pg0 = 0.0;
+    for (int i = 0; i < K; ++i) {
+        fr[i] = !((y[i] <= 0.0 && g[i] > 0.0) || (y[i] >= 1.0 && g[i] < 0.0));
+        if (fr[i]) pg0 += g[i] * g[i];
+    }
+    pg0 = sqrt(pg0);
+    if (!isfinite(f) || !isfinite(pg0)) status |= ORC_NONFINITE;
+    if (pg0 == 0.0 && !(status & ORC_NONFINITE)) status |= ORC_CONVERGED;
+
+    while (!(status & (ORC_CONVERGED | ORC_NONFINITE | ORC_NOT_PD))) {
+        if (iters >= max_iter) {
+            status |= ORC_MAXITER;
+            break;
+        }
+        /* free set and two-loop recursion restricted to it */
+        for (int i = 0; i < K; ++i) {
+            fr[i] = !((y[i] <= 0.0 && g[i] > 0.0) || (y[i] >= 1.0 && g[i] < 0.0));
+            q[i] = fr[i] ? g[i] : 0.0;
+        }
+        int used = 0;
+        double gamma = 1.0;
+        int gamma_set = 0;
+        for (int c = 0; c < npairs; ++c) {
+            int j = ((newest - c) % m + m) % m;
+            const double *sj = S + (size_t)j * K, *tj = T + (size_t)j * K;
+            double st_ = orc_dot_masked(sj, tj, fr, K);
+            double ss = orc_dot_masked(sj, sj, fr, K), tt = orc_dot_masked(tj, tj, fr, K);
+            if (!(st_ > 1e-12 * sqrt(ss) * sqrt(tt)) || tt == 0.0) {
+                rho[j] = 0.0;
+                continue;
+            }
+            rho[j] = 1.0 / st_;
+            if (!gamma_set) {
+                gamma = st_ / tt;
+                gamma_set = 1;
+            }
+            alph[j] = rho[j] * orc_dot_masked(sj, q, fr, K);
+            for (int i = 0; i < K; ++i)
+                if (fr[i]) q[i] -= alph[j] * tj[i];
+            ++used;
+        }
+        for (int i = 0; i < K; ++i) q[i] *= gamma;
+        for (int c = npairs - 1; c >= 0; --c) {
+            int j = ((newest - c) % m + m) % m;
+            if (rho[j] == 0.0) continue;
+            const double *sj = S + (size_t)j * K, *tj = T + (size_t)j * K;
+            double be = rho[j] * orc_dot_masked(tj, q, fr, K);
+            for (int i = 0; i < K; ++i)
+                if (fr[i]) q[i] += sj[i] * (alph[j] - be);
+        }
+        double pg = 0.0, pinf = 0.0;
+        int finite = 1;
+        for (int i = 0; i < K; ++i) {
+            p[i] = fr[i] ? -q[i] : 0.0;
+            pg += p[i] * g[i];
+            if (!isfinite(p[i])) finite = 0;
+        }
+        if (!(pg < 0.0) || !finite) {
+            npairs = 0;
+            newest = -1;
+            used = 0;
+            for (int i = 0; i < K; ++i) p[i] = fr[i] ? -g[i] : 0.0;
+        }
+        for (int i = 0; i < K; ++i)
+            if (fabs(p[i]) > pinf) pinf = fabs(p[i]);
+        double alpha = used ? 1.0 : (pinf > 1.0 ? 1.0 / pinf : 1.0);
+
+        /* projected backtracking line search with the Armijo condition */
+        int accepted = 0;
+        for (int bt = 0; bt <= max_backtracks; ++bt) {
+            double dec = 0.0;
+            for (int i = 0; i < K; ++i) {
+                double v = y[i] + alpha * p[i];
+                yt[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+                dec += g[i] * (yt[i] - y[i]);
+            }
+            st = orc_eval_internal(&o, yt, &ft, gt);
+            if (st < 0) {
+                free(buf);
+                free(fr);
+                return st;
+            }
+            if (!(st & ORC_NOT_PD) && isfinite(ft) && ft <= f + c1 * dec) {
+                accepted = 1;
+                break;
+            }
+            alpha *= 0.5;
+        }
+        if (!accepted) {
+            status |= ORC_LS_FAIL;
+            break;
+        }
+        /* curvature pair */
+        double sdt = 0.0, ss = 0.0, tt = 0.0;
+        for (int i = 0; i < K; ++i) {
+            double si = yt[i] - y[i], ti = gt[i] - g[i];
+            sdt += si * ti;
+            ss += si * si;
+            tt += ti * ti;
+        }
+        if (sdt > 1e-12 * sqrt(ss) * sqrt(tt)) {
+            newest = (newest + 1) % m;
+            for (int i = 0; i < K; ++i) {
+                S[(size_t)newest * K + i] = yt[i] - y[i];
+                T[(size_t)newest * K + i] = gt[i] - g[i];
+            }
+            if (npairs < m) ++npairs;
+        }
+        memcpy(y, yt, sizeof(double) * K);
+        memcpy(g, gt, sizeof(double) * K);
+        f = ft;
+        ++iters;
+        double pgn = 0.0;
+        for (int i = 0; i < K; ++i)
+            if (!((y[i] <= 0.0 && g[i] > 0.0) || (y[i] >= 1.0 && g[i] < 0.0))) pgn += g[i] * g[i];
+        if (sqrt(pgn) <= gtol * pg0) status |= ORC_CONVERGED;
+    }
+    for (int i = 0; i < K; ++i) x[i] = lo[i] + y[i] * (hi[i] - lo[i]);
+    if (fout) *fout = f;
+    if (iters_out) *iters_out = iters;
+    if (nevals_out) *nevals_out = o.nevals;
+    free(buf);
+    free(fr);
+    return status;
+}

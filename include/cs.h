@@ -1,0 +1,197 @@
+/*
+ * cs.h -- C ABI of the MI355X (gfx950) library for the clustered spectral likelihood of
+ * parametric CMB component separation (arXiv 2604.08463).
+ *
+ * Every entry point is extern "C", takes plain pointers and sizes, never throws, and reports
+ * argument errors synchronously through cs_status.  Unless a parameter is marked "host", a
+ * pointer is a DEVICE pointer (HIP global memory of the current device).  "stream" is a
+ * hipStream_t passed as void* (NULL = the legacy default stream).  The library never allocates
+ * device memory: the caller provides every buffer, including the workspaces.
+ *
+ * Method (paper Sec. 2.1-2.3, Sec. 3.3.1):
+ *   For pixel p with spectral parameters beta_p = (beta_d, T_d, beta_s), each read from its own
+ *   cluster label (one independent patching per parameter, Sec. 2.2-2.3), the F x 3 mixing
+ *   matrix A_p has the columns CMB = 1, dust modified blackbody and synchrotron power law
+ *   (eq. mixing_columns), converted from Rayleigh-Jeans to CMB units with
+ *   g(nu) = (e^y - 1)^2 / (y^2 e^y), y = h nu / (k T_CMB), and normalised to 1 at nu0.
+ *   Per Stokes parameter s in {Q, U}: M = A^T N^-1 A, b_s = A^T N^-1 d_s (eq. mle_solution),
+ *   and the objective is F = -2 ln L_spec without its constant (eq. spectral_likelihood):
+ *       F = - sum_p sum_s b_s^T M^-1 b_s.
+ *   Its gradient uses the GLS residuals r = N^-1 (d - A s_hat) with s_hat held fixed
+ *   (Sec. 3.3.1): dF/dtheta = -2 r^T (dA/dtheta) s_hat, summed over the pixels of each cluster.
+ *
+ * Parameter vectors (x, grad, lower, upper) are packed per item as
+ *   [ beta_d (K_d values) | T_d (K_T values) | beta_s (K_s values) ]
+ * and items are concatenated; cs_problem_param_offsets returns the item offsets.
+ */
+#ifndef CS_H
+#define CS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cs_problem cs_problem; /* opaque handle in host memory */
+
+typedef enum {
+    CS_OK = 0,
+    CS_E_INVALID = 1,     /* bad argument, shape or size                                    */
+    CS_E_LABEL = 2,       /* label outside [0, K_j) or excluded (-1) for only some parameters */
+    CS_E_WORKSPACE = 3,   /* workspace missing, misaligned or too small                      */
+    CS_E_HIP = 4,         /* a HIP runtime call failed; cs_last_error() has the text          */
+    CS_E_UNSUPPORTED = 5, /* shape outside what the kernels support (e.g. F > 32)             */
+    CS_E_STATE = 6        /* call out of order (e.g. evaluation before cs_problem_prepare)    */
+} cs_status;
+
+/* Working precision of the per-pixel data stream (d and per-pixel N^-1).
+ *   CS_FP64       : FP64 storage, FP64 frequency accumulation, FP64 solve and reductions.
+ *   CS_FP32_BULK  : FP32 storage, FP32 frequency accumulation (M, b and the adjoint sums),
+ *                   FP64 3x3 Cholesky solve, FP64 compensated per-cluster reductions.
+ *   CS_FP32_STORE : FP32 storage, FP64 accumulation, solve and reductions.  */
+typedef enum { CS_FP64 = 0, CS_FP32_BULK = 1, CS_FP32_STORE = 2 } cs_precision;
+
+/* Element type of the caller's d (and per-pixel N^-1) arrays. */
+typedef enum { CS_DTYPE_F64 = 0, CS_DTYPE_F32 = 1 } cs_dtype;
+
+/* Noise weights: one value per Stokes and band (host [2][F]) or per pixel (device [2][F][P]). */
+typedef enum { CS_NINV_BAND = 0, CS_NINV_PIXEL = 1 } cs_ninv_mode;
+
+/* per-item status bits, written to int32 status[B] */
+#define CS_ITEM_NOT_PD 1     /* some pixel's M failed the Cholesky pivot test -> F = NaN  */
+#define CS_ITEM_NONFINITE 2  /* F or a gradient entry is not finite                       */
+#define CS_ITEM_LS_FAIL 4    /* optimiser: line search exhausted its backtracks           */
+#define CS_ITEM_MAXITER 8    /* optimiser: iteration limit reached                        */
+#define CS_ITEM_CONVERGED 16 /* optimiser: projected-gradient tolerance reached           */
+
+typedef struct {
+    int32_t nfreq;  /* F, 1..32                                                         */
+    int32_t npix;   /* P >= 1: pixels per item (before exclusion)                       */
+    int32_t nitems; /* B >= 1: realizations / configurations / parameter points         */
+    const double *freqs_ghz;  /* host [F] band centres (delta bandpasses), > 0          */
+    double nu0_dust_ghz;      /* dust reference frequency (353 in the workloads)        */
+    double nu0_sync_ghz;      /* synchrotron reference frequency (23)                   */
+    double tcmb_k;            /* CMB temperature (2.7255)                               */
+    cs_precision precision;
+    cs_dtype d_dtype;
+    const void *d;            /* device [B][2][F][P] uK_CMB, pixel fastest               */
+    int64_t d_item_stride;    /* elements between items; 0 = one sky shared by all items */
+    cs_ninv_mode ninv_mode;
+    const double *ninv_band;  /* host [2][F] uK^-2 (> 0), used when ninv_mode = BAND     */
+    const void *ninv_pixel;   /* device [B][2][F][P] (dtype d_dtype, >= 0) when PIXEL    */
+    int64_t ninv_item_stride; /* elements between items; 0 = shared                      */
+    const int32_t *labels;    /* device [B][3][P]: cluster of each pixel for beta_d, T_d,
+                                 beta_s; -1 on all three = pixel excluded (mask)          */
+    int64_t labels_item_stride; /* elements between items; 0 = one labelling for all     */
+    const int32_t *nclusters; /* host [B][3]: K_d, K_T, K_s >= 1 of each item (equal for
+                                 all items when labels are shared)                        */
+} cs_problem_desc;
+
+/* Validates the descriptor on the host and copies the host arrays (freqs, ninv_band,
+ * nclusters).  The device arrays d, ninv_pixel and labels are only read by
+ * cs_problem_prepare.  Ownership of *out passes to the caller (cs_problem_destroy). */
+cs_status cs_problem_create(const cs_problem_desc *desc, cs_problem **out);
+
+/* host [B+1]: offset of each item's packed parameter vector; host_off[B] = total length. */
+cs_status cs_problem_param_offsets(const cs_problem *prob, int64_t *host_off);
+
+/* Device workspace needed by cs_problem_prepare and every evaluation (an upper bound that
+ * depends only on the descriptor).  The caller owns the buffer; it must be 256-byte aligned
+ * and stay alive and untouched until cs_problem_destroy. */
+cs_status cs_problem_workspace_bytes(const cs_problem *prob, size_t *bytes);
+
+/* Segment preparation, once per clustering (paper Sec. 2.2-2.3: patches are disjoint pixel
+ * sets, one patching per parameter).  On the device: validates the labels, orders the
+ * included pixels by (l_d, l_T, l_s, p), cuts the order into 64-pixel chunks and constant-
+ * label runs (segments), builds each labelling's segment CSR, and packs d (and per-pixel
+ * N^-1) into the workspace in that order and in the working precision.  Synchronises the
+ * stream.  Returns CS_E_LABEL on a bad label.  After it returns, d / ninv_pixel / labels are
+ * no longer read. */
+cs_status cs_problem_prepare(cs_problem *prob, void *workspace, size_t bytes, void *stream);
+
+/* host: number of included pixels and of segments of an item (after prepare). */
+cs_status cs_problem_item_info(const cs_problem *prob, int32_t item, int64_t *n_included,
+                               int64_t *n_segments);
+
+/* Segment structure of one labelling (0 = beta_d, 1 = T_d, 2 = beta_s) of one item, for
+ * bit-exact checks: perm[n_included] lists the included pixel indices grouped by cluster,
+ * ascending pixel index inside a cluster (a stable sort by label); offsets[K_j + 1] is the
+ * exclusive prefix sum of cluster sizes.  Device outputs; enqueued on the stream. */
+cs_status cs_problem_segments(cs_problem *prob, int32_t item, int32_t labeling, int32_t *perm,
+                              int32_t *offsets, void *stream);
+
+/* neg2logL[B] = F of each item at x (packed, FP64).  status[B] (nullable) gets the item bits.
+ * Asynchronous on the stream; no allocation; capturable in a HIP graph. */
+cs_status cs_likelihood(cs_problem *prob, const double *x, double *neg2logL, int32_t *status,
+                        void *stream);
+
+/* As cs_likelihood, plus grad (packed like x) = dF/dx summed per cluster, and optional
+ * cluster_neg2logL (nullable, packed like x): entry k of labelling j is the sum of the
+ * per-pixel terms of F over the pixels of cluster k of labelling j (each labelling's entries
+ * sum to F).  Per-cluster sums are FP64 and compensated. */
+cs_status cs_likelihood_grad(cs_problem *prob, const double *x, double *neg2logL, double *grad,
+                             double *cluster_neg2logL, int32_t *status, void *stream);
+
+/* Batched projected L-BFGS on the device (internal box y = (x - l)/(u - l), paper App. A.1;
+ * bound clamping as in Alg. 1).  Defaults: m = 10, gtol_rel = 1e-8, max_iter = 1000,
+ * iters_per_graph = 8, max_backtracks = 30, c1 = 1e-4, fp64_polish = 1. */
+typedef struct {
+    int32_t m;               /* history pairs, 1..32                                        */
+    double gtol_rel;         /* stop when |P g|_2 <= gtol_rel |P g_0|_2 (internal units)    */
+    int32_t max_iter;        /* accepted iterations per item                                */
+    int32_t iters_per_graph; /* evaluations captured per HIP-graph replay (host polls once) */
+    int32_t max_backtracks;  /* step halvings per line search                               */
+    double c1;               /* Armijo constant                                             */
+    int32_t fp64_polish;     /* CS_FP32_BULK only: items whose line search fails continue
+                                with FP64 accumulation on the same FP32 data                */
+} cs_optim_opts;
+
+cs_status cs_optim_default_opts(cs_optim_opts *opts); /* host */
+
+/* Device workspace of the optimiser for history m. */
+cs_status cs_optimizer_workspace_bytes(const cs_problem *prob, int32_t m, size_t *bytes);
+
+/* Minimises F per item inside [lower, upper] (packed like x, lower < upper).  x: in = start
+ * point (clipped into the box), out = minimiser.  f[B], iters[B], status[B] (device) receive
+ * the final objective, accepted iterations and status bits; nevals[B] (nullable, int64) the
+ * number of evaluations.  Runs HIP-graph replays of iters_per_graph evaluations and reads one
+ * 4-byte counter back after each replay, so it synchronises the stream. */
+cs_status cs_optimize_batch(cs_problem *prob, const cs_optim_opts *opts, const double *lower,
+                            const double *upper, double *x, double *f, int32_t *iters,
+                            int32_t *status, int64_t *nevals, void *opt_workspace, size_t opt_bytes,
+                            void *stream);
+
+/* Launch schedule of the per-pixel kernel (chosen by cs_problem_autotune or set by hand). */
+typedef struct {
+    int32_t waves_per_block; /* 1, 2, 4 or 8 wavefronts of 64 lanes per workgroup        */
+    int32_t blocks_per_cu;   /* 0 = one 64-pixel unit per wavefront (no grid-stride loop);
+                                n > 0 = persistent grid of n * 256 workgroups              */
+    int32_t xcd_remap;       /* 1 = give each of the 8 XCDs a contiguous range of units    */
+} cs_schedule;
+
+cs_status cs_problem_get_schedule(const cs_problem *prob, cs_schedule *sched);
+cs_status cs_problem_set_schedule(cs_problem *prob, const cs_schedule *sched);
+
+/* Times every candidate schedule on cs_likelihood_grad at x (reps evaluations each, HIP
+ * events on the stream) and keeps the fastest; candidates producing results that differ
+ * from the default schedule's are rejected.  grad / neg2logL are scratch outputs.  Writes
+ * the chosen schedule to *best (nullable).  Synchronises the stream. */
+cs_status cs_problem_autotune(cs_problem *prob, const double *x, double *neg2logL, double *grad,
+                              int32_t reps, cs_schedule *best, void *stream);
+
+/* Kernel timing: when enabled, every per-pixel kernel launch is bracketed by a pair of HIP
+ * events on its stream; cs_problem_kernel_time sums the elapsed times of the completed
+ * launches (synchronising on the last event) and resets the counters. */
+cs_status cs_problem_set_timing(cs_problem *prob, int32_t enable);
+cs_status cs_problem_kernel_time(cs_problem *prob, double *total_ms, int64_t *launches);
+
+void cs_problem_destroy(cs_problem *prob);
+const char *cs_status_str(cs_status status);
+const char *cs_last_error(void); /* thread-local text of the last error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CS_H */

@@ -1,0 +1,480 @@
+// One batched evaluation of the spectral likelihood and its adjoint (paper Sec. 2.1, 3.3.1).
+//
+//   k_sed       per (item, cluster): SED tables of the three spectral parameters (a2)
+//   k_pixel     per 64-pixel chunk (one wavefront): label gather -> mixing matrix in registers
+//               (a3), frequency accumulation of A^T N^-1 A, A^T N^-1 d and the adjoint sums (a4),
+//               FP64 3x3 Cholesky (a5), per-pixel gradient (a6), run-segmented wave reduction
+//               (a7, first level)
+//   k_fin_grad  per (item, cluster): compensated sum over the cluster's segments (a7)
+//   k_fin_f     per item: compensated sum of F and the status word (a7)
+//
+// Gradient without a second pass over the data.  With r_s = N^-1 (d_s - A s_hat_s) and
+// delta_k(nu) = dA/dtheta_k (only one column depends on theta_k),
+//   sum_nu r_s(nu) delta_k(nu) = h_sk - sum_j s_hat_sj G_jk,
+//   h_sk = sum_nu w d_s delta_k,   G_jk = sum_nu w a_j delta_k,
+// so dF/dtheta_k = -2 sum_s s_hat_s,col(k) (h_sk - sum_j s_hat_sj G_jk).  Both sums are
+// accumulated in the same single pass over frequency as M and b.
+#include "cs_internal.h"
+
+#ifndef CS_BAND_UNROLL
+#define CS_BAND_UNROLL 2
+#endif
+
+namespace csi {
+
+// ---------------------------------------------------------------------------------------------
+// band constants in the accumulation type
+// ---------------------------------------------------------------------------------------------
+template <typename TA>
+struct Band;
+template <>
+struct Band<double> {
+    static __device__ __forceinline__ double w(const BandDev &b, int s, int f) { return b.w[s][f]; }
+    static __device__ __forceinline__ double ld(const BandDev &b, int f) { return b.ld[f]; }
+    static __device__ __forceinline__ double ls(const BandDev &b, int f) { return b.ls[f]; }
+    static __device__ __forceinline__ double wsum(const BandDev &b, int s) { return b.wsum[s]; }
+};
+template <>
+struct Band<float> {
+    static __device__ __forceinline__ float w(const BandDev &b, int s, int f) { return b.wf[s][f]; }
+    static __device__ __forceinline__ float ld(const BandDev &b, int f) { return b.ldf[f]; }
+    static __device__ __forceinline__ float ls(const BandDev &b, int f) { return b.lsf[f]; }
+    static __device__ __forceinline__ float wsum(const BandDev &b, int s) { return b.wsumf[s]; }
+};
+
+__device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t g) {
+    int lo = 0, hi = nitems;  // largest lo with off[lo] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------------------------
+// a2: SED tables.  Rows of an item: PD[K_d][F] = (nu/nu0d)^beta_d;
+// BTDT[K_T][F][2] = ((nu/nu0d) expm1(x0)/expm1(x) g(nu)/g(nu0d),  d ln(.)/dT);
+// SS[K_s][F] = (nu/nu0s)^beta_s g(nu)/g(nu0s).  The dust column is PD * BT (eq. mixing_columns).
+// ---------------------------------------------------------------------------------------------
+template <typename TT>
+__global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int64_t ktot) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ktot) return;
+    const int item = find_item(xoff, a.nitems, g);
+    if (a.active && !a.active[item]) return;
+    const int64_t r = g - xoff[item];
+    if (r == 0) a.istatus[item] = 0;
+    const ItemDev it = a.items[item];
+    const BandDev &B = *a.band;
+    const int F = a.nfreq;
+    const double x = a.x[g];
+    TT *tab = (TT *)a.tables + it.tab_off * (int64_t)F;
+    if (r < it.k[0]) {
+        TT *o = tab + r * F;
+        for (int f = 0; f < F; ++f) o[f] = (TT)exp(x * B.ld[f]);
+    } else if (r < it.k[0] + it.k[1]) {
+        const int64_t kk = r - it.k[0];
+        TT *o = tab + (it.k[0] + 2 * kk) * F;
+        const double x0 = B.hk0d / x;
+        const double e0 = expm1(x0);
+        const double q0 = x0 / (-expm1(-x0));
+        for (int f = 0; f < F; ++f) {
+            const double xf = B.hk[f] / x;
+            o[2 * f] = (TT)(B.rd[f] * e0 / expm1(xf));
+            o[2 * f + 1] = (TT)((xf / (-expm1(-xf)) - q0) / x);
+        }
+    } else {
+        const int64_t kk = r - it.k[0] - it.k[1];
+        TT *o = tab + (it.k[0] + 2 * (int64_t)it.k[1] + kk) * F;
+        for (int f = 0; f < F; ++f) o[f] = (TT)(exp(x * B.ls[f]) * B.gs[f]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// a3-a7 (first level): the per-pixel kernel
+// ---------------------------------------------------------------------------------------------
+template <typename TA>
+struct WAcc {  // accumulators of one weight set: M (upper triangle) and G_jk
+    TA m00, m01, m02, m11, m12, m22;
+    TA g01, g02, g03, g11, g12, g13, g21, g22, g23;
+};
+template <typename TA>
+struct SAcc {  // accumulators of one Stokes parameter: b and h
+    TA b0, b1, b2, h1, h2, h3;
+};
+
+__device__ __forceinline__ uint64_t lanemask_le(int lane) {
+    return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+
+// WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
+template <typename TS, typename TA, bool GRAD, int WM, int FM>
+__global__ __launch_bounds__(256) void k_pixel(const EvalArgs a) {
+    constexpr int NW = (WM == 0) ? 1 : 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = a.waves_per_block;
+    const int64_t nb = gridDim.x;
+    int64_t lb = blockIdx.x;
+    if (a.xcd_remap) {  // blocks are dealt round-robin to the XCDs: give each XCD a contiguous range
+        const int64_t x = lb % kNumXcd, i = lb / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
+        lb = x * q + (x < r ? x : r) + i;
+    }
+    const BandDev &B = *a.band;
+    const int F = a.nfreq;
+    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
+        const int2 un = a.units[u];
+        const int item = __builtin_amdgcn_readfirstlane(un.x);
+        const int chunk = __builtin_amdgcn_readfirstlane(un.y);
+        if (a.active && !a.active[item]) continue;
+        const ItemDev &it = a.items[item];
+        const LayoutDev &L = a.layouts[it.layout];
+        const uint64_t head = L.head[chunk];
+        const int segbase = L.seg_base[chunk];
+        const int nvalid = L.n_incl - chunk * kChunk;
+        const bool valid = lane < nvalid;
+        const int segl = __popcll(head & lanemask_le(lane)) - 1;
+        const int4 lab = L.seg_lab[segbase + segl];
+
+        const TA *tab = (const TA *)a.tables + it.tab_off * (int64_t)F;
+        const TA *pd = tab + (int64_t)lab.x * F;
+        const TA *bt = tab + ((int64_t)it.k[0] + 2 * (int64_t)lab.y) * F;
+        const TA *ss = tab + ((int64_t)it.k[0] + 2 * (int64_t)it.k[1] + lab.z) * F;
+        const int64_t cbase = (it.dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+        const TS *dq = (const TS *)a.dpack + cbase;
+        const TS *du = dq + (int64_t)F * kChunk;
+        const TS *wq = (WM == 2) ? (const TS *)a.wpack + cbase : nullptr;
+        const TS *wu = (WM == 2) ? wq + (int64_t)F * kChunk : nullptr;
+
+        WAcc<TA> A[NW];
+        SAcc<TA> S[2];
+#pragma unroll
+        for (int n = 0; n < NW; ++n) A[n] = WAcc<TA>{};
+        S[0] = SAcc<TA>{};
+        S[1] = SAcc<TA>{};
+
+        // FM is the compile-time band count (kFMax = generic: the runtime F).  A partial unroll
+        // keeps a few bands of loads in flight without hoisting the whole band loop's loads
+        // into registers (that would drop occupancy to one wavefront per SIMD).
+        const int nf = (FM == kFMax) ? F : FM;
+#pragma unroll CS_BAND_UNROLL
+        for (int f = 0; f < nf; ++f) {
+            const int fc = f;
+            const TA d0 = (TA)dq[fc * kChunk];
+            const TA d1 = (TA)du[fc * kChunk];
+            const TA ad = pd[fc] * bt[2 * fc];
+            const TA dt = bt[2 * fc + 1];
+            const TA as = ss[fc];
+            const TA lgd = Band<TA>::ld(B, f);
+            const TA lgs = Band<TA>::ls(B, f);
+            TA w[2];
+            if (WM == 2) {
+                w[0] = (TA)wq[fc * kChunk];
+                w[1] = (TA)wu[fc * kChunk];
+            } else {
+                w[0] = Band<TA>::w(B, 0, f);
+                w[1] = Band<TA>::w(B, 1, f);
+            }
+#pragma unroll
+            for (int n = 0; n < NW; ++n) {
+                const TA wn = w[n];
+                const TA wad = wn * ad, was = wn * as;
+                WAcc<TA> &c = A[n];
+                if (WM == 2) c.m00 += wn;
+                c.m01 += wad;
+                c.m02 += was;
+                c.m11 = fma(wad, ad, c.m11);
+                c.m12 = fma(wad, as, c.m12);
+                c.m22 = fma(was, as, c.m22);
+                if (GRAD) {
+                    const TA c1 = wad * lgd, c2 = wad * dt, c3 = was * lgs;
+                    c.g01 += c1;
+                    c.g02 += c2;
+                    c.g03 += c3;
+                    c.g11 = fma(c1, ad, c.g11);
+                    c.g12 = fma(c2, ad, c.g12);
+                    c.g13 = fma(c3, ad, c.g13);
+                    c.g21 = fma(c1, as, c.g21);
+                    c.g22 = fma(c2, as, c.g22);
+                    c.g23 = fma(c3, as, c.g23);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int n = (NW == 1) ? 0 : s;
+                const TA dv = s ? d1 : d0;
+                const TA wn = w[n];
+                const TA wad = wn * ad, was = wn * as;
+                SAcc<TA> &c = S[s];
+                c.b0 = fma(wn, dv, c.b0);
+                c.b1 = fma(wad, dv, c.b1);
+                c.b2 = fma(was, dv, c.b2);
+                if (GRAD) {
+                    c.h1 = fma(wad * lgd, dv, c.h1);
+                    c.h2 = fma(wad * dt, dv, c.h2);
+                    c.h3 = fma(was * lgs, dv, c.h3);
+                }
+            }
+        }
+
+        // a5: FP64 Cholesky of each weight set's M, then per Stokes z = L^-1 b, b^T M^-1 b = z.z,
+        // s_hat = L^-T z; a6: gradient from h and G.
+        double fpix = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        bool ok = true;
+#pragma unroll
+        for (int n = 0; n < NW; ++n) {
+            const WAcc<TA> &c = A[n];
+            const double m00 = (WM == 2) ? (double)c.m00 : (double)Band<TA>::wsum(B, n);
+            const double m01 = c.m01, m02 = c.m02, m11 = c.m11, m12 = c.m12, m22 = c.m22;
+            const double l00 = sqrt(m00);
+            const double i00 = 1.0 / l00;
+            const double l10 = m01 * i00, l20 = m02 * i00;
+            const double p1 = m11 - l10 * l10;
+            const double l11 = sqrt(p1);
+            const double i11 = 1.0 / l11;
+            const double l21 = (m12 - l20 * l10) * i11;
+            const double p2 = m22 - l20 * l20 - l21 * l21;
+            const double l22 = sqrt(p2);
+            const double i22 = 1.0 / l22;
+            ok = ok && (m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (NW == 2 && s != n) continue;
+                const SAcc<TA> &q = S[s];
+                const double b0 = q.b0, b1 = q.b1, b2 = q.b2;
+                const double z0 = b0 * i00;
+                const double z1 = (b1 - l10 * z0) * i11;
+                const double z2 = (b2 - l20 * z0 - l21 * z1) * i22;
+                fpix -= z0 * z0 + z1 * z1 + z2 * z2;
+                if (GRAD) {
+                    const double s2 = z2 * i22;
+                    const double s1 = (z1 - l21 * s2) * i11;
+                    const double s0 = (z0 - l10 * s1 - l20 * s2) * i00;
+                    const double e1 = (double)q.h1 - (s0 * (double)c.g01 + s1 * (double)c.g11 + s2 * (double)c.g21);
+                    const double e2 = (double)q.h2 - (s0 * (double)c.g02 + s1 * (double)c.g12 + s2 * (double)c.g22);
+                    const double e3 = (double)q.h3 - (s0 * (double)c.g03 + s1 * (double)c.g13 + s2 * (double)c.g23);
+                    g1 -= 2.0 * s1 * e1;
+                    g2 -= 2.0 * s1 * e2;
+                    g3 -= 2.0 * s2 * e3;
+                }
+            }
+        }
+        if (!valid) {
+            fpix = 0.0;
+            g1 = g2 = g3 = 0.0;
+        } else if (!ok) {
+            fpix = g1 = g2 = g3 = __builtin_nan("");
+        }
+        const uint64_t bad = __ballot(valid && !ok);
+        if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
+
+        // a7 (first level): inclusive scan inside each constant-label run of the wavefront;
+        // the run's last lane holds the run total.
+        const int start = 63 - __clzll(head & lanemask_le(lane));
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double of = __shfl_up(fpix, off, 64);
+            double o1 = 0, o2 = 0, o3 = 0;
+            if (GRAD) {
+                o1 = __shfl_up(g1, off, 64);
+                o2 = __shfl_up(g2, off, 64);
+                o3 = __shfl_up(g3, off, 64);
+            }
+            if (lane - off >= start) {
+                fpix += of;
+                if (GRAD) {
+                    g1 += o1;
+                    g2 += o2;
+                    g3 += o3;
+                }
+            }
+        }
+        const bool last = (lane == 63) || ((head >> (lane + 1)) & 1ull);
+        if (last) {
+            double *o = a.partials + (it.part_off + segbase + segl) * 4;
+            o[0] = fpix;
+            o[1] = g1;
+            o[2] = g2;
+            o[3] = g3;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// a7 (second level): deterministic compensated sums over each cluster's segments
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void neu_add(double &s, double &c, double v) {
+    const double t = s + v;
+    if (fabs(s) >= fabs(v))
+        c += (s - t) + v;
+    else
+        c += (v - t) + s;
+    s = t;
+}
+
+__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int64_t ktot, double *grad,
+                                                  double *cluster_f) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ktot) return;
+    const int item = find_item(xoff, a.nitems, g);
+    if (a.active && !a.active[item]) return;
+    const ItemDev &it = a.items[item];
+    const LayoutDev &L = a.layouts[it.layout];
+    int64_t r = g - xoff[item];
+    int j = 0;
+    if (r >= it.k[0]) {
+        r -= it.k[0];
+        j = 1;
+        if (r >= it.k[1]) {
+            r -= it.k[1];
+            j = 2;
+        }
+    }
+    const int32_t *perm = L.seg_perm[j];
+    const int b = L.seg_off[j][r], e = L.seg_off[j][r + 1];
+    double gs = 0, gc = 0, fs = 0, fc = 0;
+    for (int i = b; i < e; ++i) {
+        const double *q = a.partials + (it.part_off + perm[i]) * 4;
+        if (grad) neu_add(gs, gc, q[1 + j]);
+        if (cluster_f) neu_add(fs, fc, q[0]);
+    }
+    if (grad) {
+        const double v = gs + gc;
+        grad[g] = v;
+        if (!isfinite(v)) atomicOr(&a.istatus[item], (int)CS_ITEM_NONFINITE);
+    }
+    if (cluster_f) cluster_f[g] = fs + fc;
+}
+
+__global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
+    const int item = blockIdx.x;
+    if (a.active && !a.active[item]) return;
+    const ItemDev &it = a.items[item];
+    const LayoutDev &L = a.layouts[it.layout];
+    const int n = L.nseg;
+    double s = 0, c = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) neu_add(s, c, a.partials[(it.part_off + i) * 4]);
+    __shared__ double ss[256], sc[256];
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double s1 = ss[threadIdx.x], c1 = sc[threadIdx.x];
+            neu_add(s1, c1, ss[threadIdx.x + st]);
+            ss[threadIdx.x] = s1;
+            sc[threadIdx.x] = c1 + sc[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int st = a.istatus[item];
+        double v = ss[0] + sc[0];
+        if (st & CS_ITEM_NOT_PD) v = __builtin_nan("");
+        else if (!isfinite(v)) st |= CS_ITEM_NONFINITE;
+        neg2logl[item] = v;
+        if (status) status[item] = st;
+        a.istatus[item] = st;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+template <typename TS, typename TA, bool GRAD>
+static void launch_pixel_t(int wm, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (wm == 0) {
+        if (F == 15)
+            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, 15>), grid, block, 0, s, a);
+        else if (F == 22)
+            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, 22>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, kFMax>), grid, block, 0, s, a);
+    } else if (wm == 1) {
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, kFMax>), grid, block, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2, kFMax>), grid, block, 0, s, a);
+    }
+}
+
+template <typename TS, typename TA>
+static void launch_pixel_g(bool grad, int wm, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (grad)
+        launch_pixel_t<TS, TA, true>(wm, F, grid, block, s, a);
+    else
+        launch_pixel_t<TS, TA, false>(wm, F, grid, block, s, a);
+}
+
+cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
+                      double *cluster_f, int32_t *status, bool want_grad, cs_precision mode, hipStream_t s) {
+    const WsLayout &w = p->ws;
+    EvalArgs a;
+    a.units = (const int2 *)(p->wsp + w.units);
+    a.nunits = p->nunits;
+    a.items = (const ItemDev *)(p->wsp + w.items);
+    a.layouts = (const LayoutDev *)(p->wsp + w.layouts);
+    a.dpack = p->wsp + w.dpack;
+    a.wpack = p->wsp + w.wpack;
+    a.tables = p->wsp + w.tables;
+    a.band = (const BandDev *)(p->wsp + w.band);
+    a.partials = (double *)(p->wsp + w.partials);
+    a.istatus = (int32_t *)(p->wsp + w.istatus);
+    a.active = active;
+    a.x = x;
+    a.nitems = p->B;
+    a.nfreq = p->F;
+    a.xcd_remap = p->sched.xcd_remap;
+    a.waves_per_block = p->sched.waves_per_block;
+    const int64_t ktot = p->xoff[p->B];
+    const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
+    const bool t32 = (mode == CS_FP32_BULK);
+    const unsigned kblocks = (unsigned)((ktot + 255) / 256);
+
+    if (t32)
+        hipLaunchKernelGGL(k_sed<float>, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot);
+    else
+        hipLaunchKernelGGL(k_sed<double>, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot);
+    CSI_HIP(hipGetLastError());
+
+    const int wpb = p->sched.waves_per_block;
+    int64_t nblocks = (p->nunits + wpb - 1) / wpb;
+    if (p->sched.blocks_per_cu > 0) nblocks = std::min<int64_t>(nblocks, (int64_t)p->sched.blocks_per_cu * kNumCu);
+    if (nblocks < 1) nblocks = 1;
+    const dim3 grid((unsigned)nblocks), block((unsigned)(64 * wpb));
+    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->timing) {
+        if (p->events_used == p->events.size()) {
+            hipEvent_t x0, x1;
+            CSI_HIP(hipEventCreate(&x0));
+            CSI_HIP(hipEventCreate(&x1));
+            p->events.emplace_back(x0, x1);
+        }
+        e0 = p->events[p->events_used].first;
+        e1 = p->events[p->events_used].second;
+        ++p->events_used;
+        CSI_HIP(hipEventRecord(e0, s));
+    }
+    if (mode == CS_FP64)
+        launch_pixel_g<double, double>(want_grad, wm, p->F, grid, block, s, a);
+    else if (mode == CS_FP32_BULK)
+        launch_pixel_g<float, float>(want_grad, wm, p->F, grid, block, s, a);
+    else
+        launch_pixel_g<float, double>(want_grad, wm, p->F, grid, block, s, a);
+    CSI_HIP(hipGetLastError());
+    if (p->timing) CSI_HIP(hipEventRecord(e1, s));
+
+    if (want_grad || cluster_f) {
+        hipLaunchKernelGGL(k_fin_grad, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot, want_grad ? grad : nullptr,
+                           cluster_f);
+        CSI_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fin_f, dim3(p->B), dim3(256), 0, s, a, neg2logl, status);
+    CSI_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+}  // namespace csi

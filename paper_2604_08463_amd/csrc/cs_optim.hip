@@ -1,0 +1,482 @@
+// Batched projected L-BFGS on the device (a8), driven by HIP-graph replays (a9).
+//
+// Every item (realization / configuration) runs its own optimisation in the internal box
+// y = (x - l)/(u - l) in [0,1]^K (paper App. A.1); trial points are clamped to the box, the
+// bound logic of Alg. 1.  One graph replay holds `iters_per_graph` steps; a step is one batched
+// evaluation of every active item followed by k_opt_update, a small state machine per item:
+//   INIT / REINIT : take F, g at the start point (REINIT keeps the curvature pairs)
+//   SEARCH        : Armijo test of the pending trial; accept -> curvature pair, convergence
+//                   test, new direction; reject -> halve the step (at most max_backtracks)
+//   DONE          : converged, line-search failure, iteration limit or bad evaluation
+// The direction is the two-loop recursion restricted to the free set (variables not held at a
+// bound by the sign of their gradient).  Items that finish are masked out of the evaluation
+// kernels through active[].  The host reads one counter after each replay.
+#include "cs_internal.h"
+
+namespace csi {
+
+enum : int32_t { ST_INIT = 0, ST_REINIT = 1, ST_SEARCH = 2, ST_DONE = 3 };
+
+struct OptItem {
+    double f, pg0, alpha, dec;
+    int64_t nevals;
+    int32_t state, status, iter, nbt, npairs, newest, pad0, pad1;
+};
+
+struct OptArgs {
+    OptItem *st;
+    int32_t *active;
+    int32_t *nactive;
+    const double *fe;      // [B] objective at the trial (evaluation output)
+    const int32_t *estat;  // [B] evaluation status
+    const double *ge;      // [Ktot] physical gradient at the trial (evaluation output)
+    double *y, *g, *p, *yt, *xt;  // [Ktot]
+    double *S, *T;         // [m][Ktot]
+    const double *lo, *hi;
+    const int64_t *xoff;
+    int64_t ktot;
+    int32_t m, max_iter, max_backtracks, pad;
+    double gtol, c1;
+};
+
+constexpr int kOptThreads = 256;
+
+// deterministic block sum of N values (fixed shuffle tree, then waves in order)
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[kOptThreads / 64]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double x = v[n];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[n][wave] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double x = 0;
+#pragma unroll
+        for (int w = 0; w < kOptThreads / 64; ++w) x += sh[n][w];
+        v[n] = x;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double x = sh[0];
+#pragma unroll
+    for (int w = 1; w < kOptThreads / 64; ++w) x = fmax(x, sh[w]);
+    __syncthreads();
+    return x;
+}
+
+__device__ __forceinline__ bool is_free(double y, double g) {
+    return !((y <= 0.0 && g > 0.0) || (y >= 1.0 && g < 0.0));
+}
+
+__global__ __launch_bounds__(kOptThreads) void k_opt_init(OptArgs a, const double *x0, int32_t nitems) {
+    const int item = blockIdx.x;
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    for (int64_t i = threadIdx.x; i < K; i += blockDim.x) {
+        const double l = a.lo[o + i], u = a.hi[o + i];
+        double yi = (x0[o + i] - l) / (u - l);
+        yi = yi < 0.0 ? 0.0 : (yi > 1.0 ? 1.0 : yi);
+        a.y[o + i] = yi;
+        a.yt[o + i] = yi;
+        a.xt[o + i] = l + yi * (u - l);
+    }
+    if (threadIdx.x == 0) {
+        OptItem s{};
+        s.state = ST_INIT;
+        a.st[item] = s;
+        a.active[item] = 1;
+        if (item == 0) *a.nactive = nitems;
+    }
+}
+
+__global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
+    const int item = blockIdx.x;
+    if (!a.active[item]) return;
+    __shared__ double red[8][kOptThreads / 64];
+    __shared__ double rho[32], alp[32];
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
+    double *y = a.y + o, *g = a.g + o, *p = a.p + o, *yt = a.yt + o, *xt = a.xt + o;
+    OptItem s = a.st[item];  // every thread holds the same copy
+    s.nevals += 1;
+    const double fe = a.fe[item];
+    const int32_t est = a.estat[item];
+    const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
+    int32_t finish = 0;
+    bool need_dir = false;
+
+    if (s.state == ST_INIT || s.state == ST_REINIT) {
+        if (!evalok) {
+            finish = est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE);
+            if (!finish) finish = CS_ITEM_NONFINITE;
+        } else {
+            double v[1] = {0.0};
+            for (int64_t i = tid; i < K; i += nt) {
+                const double gi = ge[i] * (hi[i] - lo[i]);
+                g[i] = gi;
+                if (is_free(y[i], gi)) v[0] += gi * gi;
+            }
+            block_sum<1>(v, red);
+            s.f = fe;
+            if (s.state == ST_INIT) {
+                s.pg0 = sqrt(v[0]);
+                if (!isfinite(s.pg0)) finish = CS_ITEM_NONFINITE;
+                else if (s.pg0 == 0.0) finish = CS_ITEM_CONVERGED;
+            }
+            if (!finish && s.iter >= a.max_iter) finish = CS_ITEM_MAXITER;
+            need_dir = !finish;
+        }
+    } else if (s.state == ST_SEARCH) {
+        if (evalok && fe <= s.f + a.c1 * s.dec) {
+            // curvature pair s = yt - y, t = g_trial - g (internal gradient)
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int64_t i = tid; i < K; i += nt) {
+                const double si = yt[i] - y[i], ti = ge[i] * (hi[i] - lo[i]) - g[i];
+                v[0] += si * ti;
+                v[1] += si * si;
+                v[2] += ti * ti;
+            }
+            block_sum<3>(v, red);
+            const bool keep = v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2]);
+            const int nw = keep ? (s.newest + 1) % a.m : s.newest;
+            double *Sn = a.S + (int64_t)nw * a.ktot + o, *Tn = a.T + (int64_t)nw * a.ktot + o;
+            double pg[1] = {0.0};
+            for (int64_t i = tid; i < K; i += nt) {
+                const double gi = ge[i] * (hi[i] - lo[i]);
+                if (keep) {
+                    Sn[i] = yt[i] - y[i];
+                    Tn[i] = gi - g[i];
+                }
+                y[i] = yt[i];
+                g[i] = gi;
+                if (is_free(yt[i], gi)) pg[0] += gi * gi;
+            }
+            block_sum<1>(pg, red);
+            if (keep) {
+                s.newest = nw;
+                if (s.npairs < a.m) s.npairs += 1;
+            }
+            s.f = fe;
+            s.iter += 1;
+            if (sqrt(pg[0]) <= a.gtol * s.pg0)
+                finish = CS_ITEM_CONVERGED;
+            else if (s.iter >= a.max_iter)
+                finish = CS_ITEM_MAXITER;
+            need_dir = !finish;
+        } else {
+            s.nbt += 1;
+            if (s.nbt > a.max_backtracks) {
+                finish = CS_ITEM_LS_FAIL;
+            } else {
+                s.alpha *= 0.5;
+            }
+        }
+    }
+
+    if (need_dir) {
+        // q = P g on the free set (kept in p), two-loop recursion restricted to the free set
+        const int np = s.npairs, m = a.m;
+        for (int64_t i = tid; i < K; i += nt) p[i] = is_free(y[i], g[i]) ? g[i] : 0.0;
+        double gamma = 1.0;
+        bool gamma_set = false;
+        int used = 0;
+        for (int c = 0; c < np; ++c) {
+            const int j = ((s.newest - c) % m + m) % m;
+            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int64_t i = tid; i < K; i += nt)
+                if (is_free(y[i], g[i])) {
+                    v[0] += Sj[i] * Tj[i];
+                    v[1] += Sj[i] * Sj[i];
+                    v[2] += Tj[i] * Tj[i];
+                }
+            block_sum<3>(v, red);
+            if (!(v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2])) || v[2] == 0.0) {
+                if (tid == 0) rho[j] = 0.0;
+                __syncthreads();
+                continue;
+            }
+            const double rj = 1.0 / v[0];
+            if (!gamma_set) {
+                gamma = v[0] / v[2];
+                gamma_set = true;
+            }
+            double sq[1] = {0.0};
+            for (int64_t i = tid; i < K; i += nt)
+                if (is_free(y[i], g[i])) sq[0] += Sj[i] * p[i];
+            block_sum<1>(sq, red);
+            const double aj = rj * sq[0];
+            for (int64_t i = tid; i < K; i += nt)
+                if (is_free(y[i], g[i])) p[i] -= aj * Tj[i];
+            if (tid == 0) {
+                rho[j] = rj;
+                alp[j] = aj;
+            }
+            __syncthreads();
+            ++used;
+        }
+        for (int64_t i = tid; i < K; i += nt) p[i] *= gamma;
+        __syncthreads();
+        for (int c = np - 1; c >= 0; --c) {
+            const int j = ((s.newest - c) % m + m) % m;
+            const double rj = rho[j];
+            if (rj == 0.0) continue;
+            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+            double tq[1] = {0.0};
+            for (int64_t i = tid; i < K; i += nt)
+                if (is_free(y[i], g[i])) tq[0] += Tj[i] * p[i];
+            block_sum<1>(tq, red);
+            const double be = rj * tq[0];
+            const double aj = alp[j];
+            for (int64_t i = tid; i < K; i += nt)
+                if (is_free(y[i], g[i])) p[i] += Sj[i] * (aj - be);
+            __syncthreads();
+        }
+        // p = -H Pg on the free set; fall back to -Pg when not a finite descent direction
+        double v[2] = {0.0, 0.0};
+        for (int64_t i = tid; i < K; i += nt) {
+            const double pi = is_free(y[i], g[i]) ? -p[i] : 0.0;
+            p[i] = pi;
+            v[0] += pi * g[i];
+            v[1] += isfinite(pi) ? 0.0 : 1.0;
+        }
+        block_sum<2>(v, red);
+        if (!(v[0] < 0.0) || v[1] != 0.0) {
+            s.npairs = 0;
+            s.newest = -1;
+            used = 0;
+            for (int64_t i = tid; i < K; i += nt) p[i] = is_free(y[i], g[i]) ? -g[i] : 0.0;
+            __syncthreads();
+        }
+        double pm = 0.0;
+        for (int64_t i = tid; i < K; i += nt) pm = fmax(pm, fabs(p[i]));
+        pm = block_max(pm, red[0]);
+        s.alpha = used ? 1.0 : (pm > 1.0 ? 1.0 / pm : 1.0);
+        s.nbt = 0;
+    }
+
+    if (!finish && s.state != ST_DONE) {
+        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y)
+        double v[1] = {0.0};
+        for (int64_t i = tid; i < K; i += nt) {
+            double t = y[i] + s.alpha * p[i];
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            yt[i] = t;
+            xt[i] = lo[i] + t * (hi[i] - lo[i]);
+            v[0] += g[i] * (t - y[i]);
+        }
+        block_sum<1>(v, red);
+        s.dec = v[0];
+        s.state = ST_SEARCH;
+    }
+    if (finish) {
+        s.status |= finish;
+        s.state = ST_DONE;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a.st[item] = s;
+        if (finish) {
+            a.active[item] = 0;
+            atomicSub(a.nactive, 1);
+        }
+    }
+}
+
+// items stopped by a line-search failure continue from their point (pairs kept) in FP64
+__global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t nitems) {
+    const int item = blockIdx.x;
+    OptItem s = a.st[item];
+    if (!(s.state == ST_DONE && (s.status & CS_ITEM_LS_FAIL))) return;
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    for (int64_t i = threadIdx.x; i < K; i += blockDim.x) {
+        a.yt[o + i] = a.y[o + i];
+        a.xt[o + i] = a.lo[o + i] + a.y[o + i] * (a.hi[o + i] - a.lo[o + i]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.status &= ~CS_ITEM_LS_FAIL;
+        s.state = ST_REINIT;
+        a.st[item] = s;
+        a.active[item] = 1;
+        atomicAdd(a.nactive, 1);
+    }
+    (void)nitems;
+}
+
+__global__ __launch_bounds__(kOptThreads) void k_opt_output(OptArgs a, double *x, double *f, int32_t *iters,
+                                                            int32_t *status, int64_t *nevals) {
+    const int item = blockIdx.x;
+    OptItem s = a.st[item];
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    for (int64_t i = threadIdx.x; i < K; i += blockDim.x)
+        x[o + i] = a.lo[o + i] + a.y[o + i] * (a.hi[o + i] - a.lo[o + i]);
+    if (threadIdx.x == 0) {
+        int32_t stt = s.status;
+        if (s.state != ST_DONE) stt |= CS_ITEM_MAXITER;  // stopped by the replay cap
+        f[item] = s.f;
+        iters[item] = s.iter;
+        status[item] = stt;
+        if (nevals) nevals[item] = s.nevals;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------------------------
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t optimizer_bytes(const cs_problem *p, int32_t m) {
+    const size_t B = (size_t)p->B, K = (size_t)p->xoff[p->B];
+    size_t t = 0;
+    t += al256(sizeof(OptItem) * B);
+    t += al256(sizeof(int32_t) * B) * 2 + al256(sizeof(int32_t));
+    t += al256(sizeof(double) * B);
+    t += al256(sizeof(double) * K) * 6;
+    t += al256(sizeof(double) * K * (size_t)m) * 2;
+    return t;
+}
+
+cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, const double *hi, double *x, double *f,
+                   int32_t *iters, int32_t *status, int64_t *nevals, void *ws, size_t bytes, hipStream_t caller) {
+    const int B = p->B;
+    const int64_t K = p->xoff[B];
+    if (bytes < optimizer_bytes(p, o->m)) {
+        set_error("optimizer workspace too small");
+        return CS_E_WORKSPACE;
+    }
+    char *w = (char *)ws;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        char *r = w + off;
+        off += al256(n);
+        return r;
+    };
+    OptArgs a;
+    a.st = (OptItem *)take(sizeof(OptItem) * B);
+    a.active = (int32_t *)take(sizeof(int32_t) * B);
+    int32_t *estat = (int32_t *)take(sizeof(int32_t) * B);
+    a.estat = estat;
+    a.nactive = (int32_t *)take(sizeof(int32_t));
+    double *fe = (double *)take(sizeof(double) * B);
+    a.fe = fe;
+    double *ge = (double *)take(sizeof(double) * K);
+    a.ge = ge;
+    a.y = (double *)take(sizeof(double) * K);
+    a.g = (double *)take(sizeof(double) * K);
+    a.p = (double *)take(sizeof(double) * K);
+    a.yt = (double *)take(sizeof(double) * K);
+    a.xt = (double *)take(sizeof(double) * K);
+    a.S = (double *)take(sizeof(double) * K * o->m);
+    a.T = (double *)take(sizeof(double) * K * o->m);
+    a.lo = lo;
+    a.hi = hi;
+    a.xoff = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)B);
+    a.ktot = K;
+    a.m = o->m;
+    a.max_iter = o->max_iter;
+    a.max_backtracks = o->max_backtracks;
+    a.gtol = o->gtol_rel;
+    a.c1 = o->c1;
+
+    CSI_HIP(hipStreamSynchronize(caller));
+    hipStream_t s;
+    CSI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    cs_status rc = CS_OK;
+    const bool was_timing = p->timing;
+    p->timing = false;  // no event records inside captured graphs
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int32_t *hcount = nullptr;
+    do {
+        hipLaunchKernelGGL(k_opt_init, dim3(B), dim3(kOptThreads), 0, s, a, x, B);
+        hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) {
+            rc = hip_fail(e0, "k_opt_init");
+            break;
+        }
+        hipError_t eh = hipHostMalloc((void **)&hcount, sizeof(int32_t), hipHostMallocDefault);
+        if (eh != hipSuccess) {
+            hcount = nullptr;
+            rc = hip_fail(eh, "hipHostMalloc");
+            break;
+        }
+        const int phases = (p->prec == CS_FP32_BULK && o->fp64_polish) ? 2 : 1;
+        // bound on replays: every item needs at most max_iter * (max_backtracks + 1) + 1 evaluations
+        const int64_t max_steps = (int64_t)(o->max_iter + 1) * (o->max_backtracks + 1) + 2;
+        for (int ph = 0; ph < phases && rc == CS_OK; ++ph) {
+            const cs_precision mode = (ph == 0) ? p->prec : CS_FP32_STORE;
+            if (ph == 1) {
+                hipLaunchKernelGGL(k_opt_repolish, dim3(B), dim3(kOptThreads), 0, s, a, B);
+                hipError_t e3 = hipGetLastError();
+                if (e3 != hipSuccess) {
+                    rc = hip_fail(e3, "k_opt_repolish");
+                    break;
+                }
+            }
+            hipError_t ecap = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (ecap != hipSuccess) {
+                rc = hip_fail(ecap, "hipStreamBeginCapture");
+                break;
+            }
+            for (int k = 0; k < o->iters_per_graph && rc == CS_OK; ++k) {
+                rc = launch_eval(p, a.xt, a.active, fe, ge, nullptr, estat, true, mode, s);
+                if (rc == CS_OK) {
+                    hipLaunchKernelGGL(k_opt_update, dim3(B), dim3(kOptThreads), 0, s, a);
+                    hipError_t eu = hipGetLastError();
+                    if (eu != hipSuccess) rc = hip_fail(eu, "k_opt_update");
+                }
+            }
+            hipError_t ec = hipStreamEndCapture(s, &graph[ph]);
+            if (rc != CS_OK) break;
+            if (ec != hipSuccess) {
+                rc = hip_fail(ec, "hipStreamEndCapture");
+                break;
+            }
+            ec = hipGraphInstantiate(&exec[ph], graph[ph], nullptr, nullptr, 0);
+            if (ec != hipSuccess) {
+                rc = hip_fail(ec, "hipGraphInstantiate");
+                break;
+            }
+            int64_t steps = 0;
+            for (;;) {
+                hipError_t e1 = hipGraphLaunch(exec[ph], s);
+                if (e1 == hipSuccess) e1 = hipMemcpyAsync(hcount, a.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+                if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+                if (e1 != hipSuccess) {
+                    rc = hip_fail(e1, "optimizer graph replay");
+                    break;
+                }
+                steps += o->iters_per_graph;
+                if (*hcount <= 0 || steps >= max_steps) break;
+            }
+        }
+        if (rc != CS_OK) break;
+        hipLaunchKernelGGL(k_opt_output, dim3(B), dim3(kOptThreads), 0, s, a, x, f, iters, status, nevals);
+        hipError_t e2 = hipGetLastError();
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        if (e2 != hipSuccess) rc = hip_fail(e2, "k_opt_output");
+    } while (false);
+    for (int ph = 0; ph < 2; ++ph) {
+        if (exec[ph]) (void)hipGraphExecDestroy(exec[ph]);
+        if (graph[ph]) (void)hipGraphDestroy(graph[ph]);
+    }
+    if (hcount) (void)hipHostFree(hcount);
+    (void)hipStreamDestroy(s);
+    p->timing = was_timing;
+    return rc;
+}
+
+}  // namespace csi

@@ -1,0 +1,250 @@
+"""GPU parity of the HIP library against the FP64 oracle (run on an MI355X)."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import skygen
+from oracle import oracle
+from tests._parity import TOL_F, compare, gpu_eval
+
+pytestmark = pytest.mark.gpu
+
+cs = pytest.importorskip("paper_2604_08463_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cs.load()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------------------------------
+# a1: segments are bit-exact
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["tiny-mask", "workload2-small", "ragged"])
+def test_segments_bit_exact(case):
+    if case == "tiny-mask":
+        sky = skygen.make_tiny(333, 15, (9, 4, 6), seed=31, mask_frac=0.25)
+    elif case == "workload2-small":
+        sky = skygen.make_config(2, npix=6000, nitems=2, k=(150, 12, 40))
+    else:
+        sky = skygen.make_config(4, nitems=5)
+    _log(f"segments {case}")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    for b in range(sky.nitems):
+        lab = sky.item_labels(b)
+        n_incl, nseg = prob.item_info(b)
+        assert n_incl == int(np.sum(lab[0] >= 0))
+        for j in range(3):
+            perm, off = prob.segments(b, j)
+            rp, ro = oracle.segments(lab[j], int(sky.nclusters[b, j]))
+            assert np.array_equal(perm.cpu().numpy(), rp)
+            assert np.array_equal(off.cpu().numpy(), ro)
+        # segments = runs of constant (l_d, l_T, l_s) in (l_d, l_T, l_s, p) order cut every 64 pixels
+        inc = np.flatnonzero(lab[0] >= 0)
+        order = inc[np.lexsort((inc, lab[2, inc], lab[1, inc], lab[0, inc]))]
+        trip = lab[:, order].T
+        heads = np.ones(len(order), dtype=bool)
+        heads[1:] = np.any(trip[1:] != trip[:-1], axis=1)
+        heads[::64] = True
+        assert nseg == int(heads.sum())
+
+
+# ------------------------------------------------------------------------------------------
+# a2-a7: FP64 path vs oracle
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nfreq", [15, 22, 4, 9, 32])
+def test_fp64_tiny_shapes(nfreq):
+    sky = skygen.make_tiny(517, nfreq, (5, 3, 4), seed=nfreq, nitems=3, mask_frac=0.1)
+    _log(f"fp64 tiny F={nfreq}")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    compare(sky, prob, "fp64")
+
+
+def test_fp64_workload1_all_points():
+    sky = skygen.make_config(1)
+    _log("fp64 workload 1 (3072 px, 64 points)")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    ef, eg, ec = compare(sky, prob, "fp64")
+    _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
+
+
+def test_fp64_workload2_full():
+    sky = skygen.make_config(2)
+    _log("fp64 workload 2 (49152 px, K=(1000,50,200), 8 points)")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    ef, eg, ec = compare(sky, prob, "fp64")
+    _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
+
+
+@pytest.mark.parametrize("precision", ["fp32_bulk", "fp32_store"])
+def test_fp32_paths_workload2(precision):
+    sky = skygen.make_config(2, nitems=4)
+    _log(f"{precision} workload 2")
+    prob = cs.Problem.from_sky(sky, precision)
+    ef, eg, ec = compare(sky, prob, precision)
+    _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
+
+
+def test_fp32_input_dtype():
+    sky = skygen.make_tiny(300, 15, (4, 2, 3), seed=41, nitems=2)
+    d32 = sky.d.to(torch.float32)
+    sky.d = d32.to(torch.float64)  # the oracle sees exactly the FP32 values
+    prob = cs.Problem.from_sky(sky, "fp64", d_dtype=torch.float32)
+    compare(sky, prob, "fp64")
+
+
+def test_separate_stokes_and_pixel_weights():
+    sky = skygen.make_tiny(400, 15, (4, 3, 2), seed=42, nitems=2)
+    sky.ninv = sky.ninv.copy()
+    sky.ninv[1] *= 1.7  # Q and U weights differ
+    prob = cs.Problem.from_sky(sky, "fp64")
+    compare(sky, prob, "fp64")
+    # per-pixel weights: the oracle gets the same [2][F][P] array
+    g = np.random.default_rng(5)
+    wpix = sky.ninv[:, :, None] * g.uniform(0.5, 2.0, (2, sky.nfreq, sky.npix))
+    prob2 = cs.Problem(sky.freqs, sky.d.cuda(), torch.as_tensor(wpix[None]).cuda(), sky.labels.cuda(),
+                       sky.nclusters, nitems=sky.nitems, precision="fp64")
+    f, gr, _, st = gpu_eval(prob2, sky, cluster=False)
+    off = sky.param_offsets()
+    for b in range(sky.nitems):
+        pr = oracle.Problem(sky.freqs, sky.item_d(b), wpix, sky.item_labels(b), sky.nclusters[b])
+        fo, go, _, so = pr.likelihood_grad(sky.x[b])
+        assert abs(f[b] - fo) <= 1e-12 * abs(fo)
+        assert np.max(np.abs(gr[off[b]:off[b + 1]] - go)) <= 1e-9 * np.max(np.abs(go))
+
+
+def test_not_pd_status_and_nan():
+    sky = skygen.make_tiny(200, 15, (2, 2, 2), seed=43, nitems=2)
+    wpix = np.repeat(sky.ninv[:, :, None], sky.npix, axis=2)
+    wpix = np.stack([wpix, wpix])
+    wpix[1, :, :, 17] = 0.0  # item 1, pixel 17: M = 0
+    prob = cs.Problem(sky.freqs, sky.d.cuda(), torch.as_tensor(wpix).cuda(), sky.labels.cuda(), sky.nclusters,
+                      nitems=2, precision="fp64")
+    f, _, _, st = gpu_eval(prob, sky, cluster=False)
+    assert st[0] == 0 and np.isfinite(f[0])
+    assert st[1] & cs.NOT_PD and np.isnan(f[1])
+
+
+def test_label_error_is_reported():
+    sky = skygen.make_tiny(100, 15, (3, 2, 2), seed=44)
+    lab = sky.labels.clone()
+    lab[0, 1, 10] = 5  # T_d label out of range
+    with pytest.raises(cs.CsError) as e:
+        cs.Problem(sky.freqs, sky.d.cuda(), sky.ninv, lab.cuda(), sky.nclusters, precision="fp64")
+    assert e.value.status == 2
+    lab = sky.labels.clone()
+    lab[0, 0, 3] = -1  # excluded for beta_d only
+    with pytest.raises(cs.CsError):
+        cs.Problem(sky.freqs, sky.d.cuda(), sky.ninv, lab.cuda(), sky.nclusters, precision="fp64")
+
+
+def test_batched_equals_per_item_and_schedules_bit_identical():
+    sky = skygen.make_config(2, npix=8000, nitems=5, k=(200, 20, 60))
+    prob = cs.Problem.from_sky(sky, "fp64")
+    f, g, cf, st = gpu_eval(prob, sky)
+    off = sky.param_offsets()
+    # one item at a time through a one-item problem
+    for b in (0, 3):
+        one = cs.Problem(sky.freqs, sky.d.cuda(), sky.ninv, sky.labels.cuda(), sky.nclusters[b:b + 1], nitems=1,
+                         precision="fp64")
+        f1, g1, _, _ = one.cs_likelihood_grad(torch.as_tensor(sky.x[b], device="cuda"))
+        assert f1.item() == f[b]
+        assert np.array_equal(g1.cpu().numpy(), g[off[b]:off[b + 1]])
+    for wpb in (1, 2, 8):
+        for bpc in (0, 2):
+            for xr in (0, 1):
+                prob.set_schedule(wpb, bpc, xr)
+                f2, g2, _, _ = gpu_eval(prob, sky, cluster=False)
+                assert np.array_equal(f2, f) and np.array_equal(g2, g)
+
+
+def test_likelihood_without_gradient_matches():
+    sky = skygen.make_config(2, npix=5000, nitems=3, k=(100, 10, 20))
+    prob = cs.Problem.from_sky(sky, "fp64")
+    f, _, _, _ = gpu_eval(prob, sky, cluster=False)
+    f2, st = prob.cs_likelihood(torch.as_tensor(sky.x_packed(), device="cuda"))
+    f2 = f2.cpu().numpy()
+    assert np.all(np.abs(f2 - f) <= 1e-13 * np.abs(f))
+
+
+def test_model_consistent_noiseless_zero_gradient():
+    sky = skygen.make_tiny(600, 15, (6, 3, 4), seed=45, noiseless=True, model_consistent=True)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    xt = sky.meta["x_true"]
+    f, g, _, _ = gpu_eval(prob, sky, x=[xt], cluster=False)
+    po = oracle.Problem.from_sky(sky)
+    chi2 = po.data_chi2()
+    assert abs(f[0] + chi2) <= 1e-12 * chi2
+    _, gp, _, _ = po.likelihood_grad(xt + 0.05)
+    assert np.max(np.abs(g)) <= 1e-9 * np.max(np.abs(gp))
+
+
+# ------------------------------------------------------------------------------------------
+# autograd
+# ------------------------------------------------------------------------------------------
+
+def test_autograd_matches_central_differences():
+    sky = skygen.make_config(3, nitems=4)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    x = torch.as_tensor(np.concatenate([[1.6, 21.0, -2.9], [1.5, 19.0, -3.1], [1.45, 23.0, -3.0], [1.7, 18.0, -2.95]]),
+                        device="cuda").requires_grad_(True)
+    f = cs.neg2logl(x, prob)
+    wts = torch.tensor([1.0, -0.5, 2.0, 0.25], dtype=torch.float64, device="cuda")
+    (f * wts).sum().backward()
+    h = 1e-6
+    fd = np.zeros(x.numel())
+    xv = x.detach().clone()
+    for i in range(x.numel()):
+        e = torch.zeros_like(xv)
+        e[i] = h
+        fp, _ = prob.cs_likelihood(xv + e)
+        fm, _ = prob.cs_likelihood(xv - e)
+        fd[i] = ((fp - fm) * wts).sum().item() / (2 * h)
+    ag = x.grad.cpu().numpy()
+    assert np.all(np.abs(ag - fd) <= 1e-5 * np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd))))
+
+
+# ------------------------------------------------------------------------------------------
+# a8: optimiser
+# ------------------------------------------------------------------------------------------
+
+def test_optimizer_fp64_matches_oracle_workload3():
+    sky = skygen.make_config(3, nitems=12)
+    _log("optimizer fp64 workload 3 (12 realizations)")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = prob.cs_optimize_batch(lo, hi, sky.x_packed())
+    x = r["x"].cpu().numpy()
+    f = r["f"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    for b in range(sky.nitems):
+        po = oracle.Problem.from_sky(sky, b)
+        xo, fo, it, ne, so = po.lbfgs(sky.x[b], sky.lower[b], sky.upper[b])
+        xb = x[3 * b:3 * b + 3]
+        assert st[b] & cs.CONVERGED, (b, st[b])
+        assert so & oracle.CONVERGED
+        assert abs(f[b] - fo) <= 1e-10 * abs(fo), (b, f[b], fo)
+        assert np.all(np.abs(xb - xo) <= 1e-4 * np.maximum(1.0, np.abs(xo))), (b, xb, xo)
+
+
+def test_optimizer_fp32_bulk_within_1e4_of_fp64():
+    sky = skygen.make_config(3, nitems=16)
+    _log("optimizer fp32_bulk vs fp64 workload 3 (16 realizations)")
+    lo, hi = sky.bounds_packed()
+    r64 = cs.Problem.from_sky(sky, "fp64").cs_optimize_batch(lo, hi, sky.x_packed())
+    r32 = cs.Problem.from_sky(sky, "fp32_bulk").cs_optimize_batch(lo, hi, sky.x_packed())
+    x64, x32 = r64["x"].cpu().numpy(), r32["x"].cpu().numpy()
+    f64, f32 = r64["f"].cpu().numpy(), r32["f"].cpu().numpy()
+    assert np.all(np.abs(x32 - x64) <= 1e-4 * np.maximum(1.0, np.abs(x64))), np.max(np.abs(x32 - x64))
+    assert np.all(np.abs(f32 - f64) <= TOL_F["fp32_bulk"] * np.abs(f64))

@@ -37,6 +37,8 @@
 #define ORC_MAXITER 8
 #define ORC_CONVERGED 16
 
+#define ORC_FLAT_REL 1e-12
+
 #define ORC_E_INVALID (-1)
 #define ORC_E_LABEL (-2)
 
@@ -332,8 +334,10 @@ int64_t orc_segments(int64_t npix, const int32_t *labels, int32_t k, int32_t *pe
  *   with gamma = s.t / t.t of the newest used pair (1 if none).  p = -(H Pg) on the free set;
  *   if p.g >= 0 or p is not finite the memory is cleared and p = -Pg.
  *   Step: alpha0 = 1, or min(1, 1/|p|_inf) when no pair was used.  Trial
- *   y(alpha) = clip(y + alpha p, 0, 1); Armijo F(y(a)) <= F(y) + c1 g.(y(a) - y); halve alpha at
- *   most max_backtracks times, else stop with LS_FAIL.
+ *   y(alpha) = clip(y + alpha p, 0, 1) is accepted on Armijo, F(y(a)) <= F(y) + c1 g.(y(a) - y),
+ *   or, where F no longer resolves the decrease, when |F(y(a)) - F(y)| <= 1e-12 |F(y)| and
+ *   g(y(a)).(y(a) - y) <= 0 (a step leaving y unchanged is rejected); alpha is halved at most
+ *   max_backtracks times, else LS_FAIL.
  *   Accept: s = y_new - y, t = g_new - g, stored when s.t > 1e-12 |s||t| (ring of m pairs).
  *   Stop when |Pg|_2 <= gtol |Pg_0|_2 (CONVERGED) or after max_iter iterations (MAXITER).
  */
@@ -470,9 +474,20 @@ int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double 
                 free(fr);
                 return st;
             }
-            if (!(st & ORC_NOT_PD) && isfinite(ft) && ft <= f + c1 * dec) {
-                accepted = 1;
-                break;
+            if (!(st & ORC_NOT_PD) && isfinite(ft)) {
+                /* Armijo, or (at the rounding floor of F) an unchanged F with the function still
+                   non-increasing at the trial point along the step */
+                double gd = 0.0, moved = 0.0;
+                for (int i = 0; i < K; ++i) {
+                    gd += gt[i] * (yt[i] - y[i]);
+                    moved += (yt[i] - y[i]) * (yt[i] - y[i]);
+                }
+                /* a step that leaves y unchanged is never accepted */
+                if (moved > 0.0 &&
+                    (ft <= f + c1 * dec || (fabs(ft - f) <= ORC_FLAT_REL * fabs(f) && gd <= 0.0))) {
+                    accepted = 1;
+                    break;
+                }
             }
             alpha *= 0.5;
         }

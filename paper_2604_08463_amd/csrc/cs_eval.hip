@@ -112,7 +112,7 @@ __device__ __forceinline__ uint64_t lanemask_le(int lane) {
 
 // WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
 template <typename TS, typename TA, bool GRAD, int WM, int FM>
-__global__ __launch_bounds__(256) void k_pixel(const EvalArgs a) {
+__global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
     constexpr int NW = (WM == 0) ? 1 : 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

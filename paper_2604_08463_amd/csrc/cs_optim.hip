@@ -5,8 +5,9 @@
 // bound logic of Alg. 1.  One graph replay holds `iters_per_graph` steps; a step is one batched
 // evaluation of every active item followed by k_opt_update, a small state machine per item:
 //   INIT / REINIT : take F, g at the start point (REINIT keeps the curvature pairs)
-//   SEARCH        : Armijo test of the pending trial; accept -> curvature pair, convergence
-//                   test, new direction; reject -> halve the step (at most max_backtracks)
+//   SEARCH        : line-search test of the pending trial (Armijo, or F unchanged to 1e-12
+//                   relative with g_trial.(y_trial - y) <= 0); accept -> curvature pair,
+//                   convergence test, new direction; reject -> halve the step (max_backtracks)
 //   DONE          : converged, line-search failure, iteration limit or bad evaluation
 // The direction is the two-loop recursion restricted to the free set (variables not held at a
 // bound by the sign of their gradient).  Items that finish are masked out of the evaluation
@@ -40,6 +41,7 @@ struct OptArgs {
 };
 
 constexpr int kOptThreads = 256;
+constexpr double kFlatRel = 1e-12;  // relative change of F below which Armijo is not resolved
 
 // deterministic block sum of N values (fixed shuffle tree, then waves in order)
 template <int N>
@@ -139,16 +141,21 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
             need_dir = !finish;
         }
     } else if (s.state == ST_SEARCH) {
-        if (evalok && fe <= s.f + a.c1 * s.dec) {
-            // curvature pair s = yt - y, t = g_trial - g (internal gradient)
-            double v[3] = {0.0, 0.0, 0.0};
+        // s = yt - y, t = g_trial - g (internal gradients): s.t, s.s, t.t and g_trial.s
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (evalok) {
             for (int64_t i = tid; i < K; i += nt) {
-                const double si = yt[i] - y[i], ti = ge[i] * (hi[i] - lo[i]) - g[i];
+                const double si = yt[i] - y[i], gti = ge[i] * (hi[i] - lo[i]), ti = gti - g[i];
                 v[0] += si * ti;
                 v[1] += si * si;
                 v[2] += ti * ti;
+                v[3] += gti * si;
             }
-            block_sum<3>(v, red);
+        }
+        block_sum<4>(v, red);
+        // Armijo, or (at the rounding floor of F) F unchanged and still non-increasing at the trial
+        const bool flat = fabs(fe - s.f) <= kFlatRel * fabs(s.f) && v[3] <= 0.0;
+        if (evalok && v[1] > 0.0 && (fe <= s.f + a.c1 * s.dec || flat)) {  // never accept a null step
             const bool keep = v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2]);
             const int nw = keep ? (s.newest + 1) % a.m : s.newest;
             double *Sn = a.S + (int64_t)nw * a.ktot + o, *Tn = a.T + (int64_t)nw * a.ktot + o;

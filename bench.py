@@ -94,11 +94,26 @@ def main():
     ap.add_argument("--no-optimizer", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="kernel-profiling run: only the timed evaluations of one precision")
+    ap.add_argument("--precision", default="fp32_bulk", choices=["fp64", "fp32_bulk", "fp32_store"])
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="HBM counter calibration: time a plain device copy of this many bytes and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(items would be sharded across GPUs by contiguous chunks; not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "launches": args.warmup + args.steps}), flush=True)
+        return
 
     import paper_2604_08463_amd as cs
     import skygen
@@ -119,7 +134,15 @@ def main():
     x = torch.as_tensor(xs, device="cuda")
     x_items = [xs[o:e] for o, e in zip(sky.param_offsets()[:-1], sky.param_offsets()[1:])]
 
-    res = {}
+    if args.profile:
+        prob = cs.Problem.from_sky(sky, args.precision)
+        wall, kms, nl, _ = time_eval(prob, x, args.steps, args.warmup)
+        ab = algorithmic_bytes(prob, sky, 8 if args.precision == "fp64" else 4)
+        print(json.dumps({"precision": args.precision, "ms_per_step": wall / args.steps * 1e3,
+                          "kernel_ms": kms / max(nl, 1), "bytes_per_launch": ab,
+                          "achieved_gbs": ab / (kms / max(nl, 1) * 1e-3) / 1e9}), flush=True)
+        return
+
     torch.cuda.synchronize()
     tp = time.perf_counter()
     p32 = cs.Problem.from_sky(sky, "fp32_bulk", d_dtype=torch.float64)

@@ -16,11 +16,31 @@
 // accumulated in the same single pass over frequency as M and b.
 #include "cs_internal.h"
 
-#ifndef CS_BAND_UNROLL
-#define CS_BAND_UNROLL 2
+#ifndef CS_WAVES_PER_EU
+#define CS_WAVES_PER_EU 1
+#endif
+#ifndef CS_BAND_GROUP
+#define CS_BAND_GROUP 2
 #endif
 
 namespace csi {
+
+// Address-space views.  Read-only data indexed uniformly across a wavefront (work units, item
+// and layout descriptors, band constants, chunk heads) is read through the constant address
+// space so that it lands in scalar registers via the scalar cache; data indexed per lane goes
+// through explicit global pointers instead of generic (flat) ones.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+    return (cptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
 
 // ---------------------------------------------------------------------------------------------
 // band constants in the accumulation type
@@ -29,17 +49,17 @@ template <typename TA>
 struct Band;
 template <>
 struct Band<double> {
-    static __device__ __forceinline__ double w(const BandDev &b, int s, int f) { return b.w[s][f]; }
-    static __device__ __forceinline__ double ld(const BandDev &b, int f) { return b.ld[f]; }
-    static __device__ __forceinline__ double ls(const BandDev &b, int f) { return b.ls[f]; }
-    static __device__ __forceinline__ double wsum(const BandDev &b, int s) { return b.wsum[s]; }
+    static __device__ __forceinline__ double w(cptr<BandDev> b, int s, int f) { return b->w[s][f]; }
+    static __device__ __forceinline__ double ld(cptr<BandDev> b, int f) { return b->ld[f]; }
+    static __device__ __forceinline__ double ls(cptr<BandDev> b, int f) { return b->ls[f]; }
+    static __device__ __forceinline__ double wsum(cptr<BandDev> b, int s) { return b->wsum[s]; }
 };
 template <>
 struct Band<float> {
-    static __device__ __forceinline__ float w(const BandDev &b, int s, int f) { return b.wf[s][f]; }
-    static __device__ __forceinline__ float ld(const BandDev &b, int f) { return b.ldf[f]; }
-    static __device__ __forceinline__ float ls(const BandDev &b, int f) { return b.lsf[f]; }
-    static __device__ __forceinline__ float wsum(const BandDev &b, int s) { return b.wsumf[s]; }
+    static __device__ __forceinline__ float w(cptr<BandDev> b, int s, int f) { return b->wf[s][f]; }
+    static __device__ __forceinline__ float ld(cptr<BandDev> b, int f) { return b->ldf[f]; }
+    static __device__ __forceinline__ float ls(cptr<BandDev> b, int f) { return b->lsf[f]; }
+    static __device__ __forceinline__ float wsum(cptr<BandDev> b, int s) { return b->wsum[s]; }
 };
 
 __device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t g) {
@@ -111,8 +131,8 @@ __device__ __forceinline__ uint64_t lanemask_le(int lane) {
 }
 
 // WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
-template <typename TS, typename TA, bool GRAD, int WM, int FM>
-__global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
+template <typename TS, typename TA, bool GRAD, int WM>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PER_EU))) void k_pixel(const EvalArgs a) {
     constexpr int NW = (WM == 0) ? 1 : 2;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -123,31 +143,36 @@ __global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
         const int64_t x = lb % kNumXcd, i = lb / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
         lb = x * q + (x < r ? x : r) + i;
     }
-    const BandDev &B = *a.band;
+    const cptr<BandDev> B = as_const(a.band);
     const int F = a.nfreq;
+    const cptr<int> units = as_const((const int *)a.units);
+    const cptr<ItemDev> items = as_const(a.items);
+    const cptr<LayoutDev> layouts = as_const(a.layouts);
     for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
-        const int2 un = a.units[u];
-        const int item = __builtin_amdgcn_readfirstlane(un.x);
-        const int chunk = __builtin_amdgcn_readfirstlane(un.y);
-        if (a.active && !a.active[item]) continue;
-        const ItemDev &it = a.items[item];
-        const LayoutDev &L = a.layouts[it.layout];
-        const uint64_t head = L.head[chunk];
-        const int segbase = L.seg_base[chunk];
-        const int nvalid = L.n_incl - chunk * kChunk;
+        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
+        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
+        if (a.active && !as_const(a.active)[item]) continue;
+        const cptr<ItemDev> it = items + item;
+        const cptr<LayoutDev> L = layouts + it->layout;
+        const uint64_t head = as_const(L->head)[chunk];
+        const int segbase = as_const(L->seg_base)[chunk];
+        const int nvalid = L->n_incl - chunk * kChunk;
         const bool valid = lane < nvalid;
         const int segl = __popcll(head & lanemask_le(lane)) - 1;
-        const int4 lab = L.seg_lab[segbase + segl];
+        const gptr<int> labp = as_global((const int *)L->seg_lab) + 4 * (int64_t)(segbase + segl);
+        const int lab_d = labp[0], lab_t = labp[1], lab_s = labp[2];
+        const int64_t kd = it->k[0], kt = it->k[1];
 
-        const TA *tab = (const TA *)a.tables + it.tab_off * (int64_t)F;
-        const TA *pd = tab + (int64_t)lab.x * F;
-        const TA *bt = tab + ((int64_t)it.k[0] + 2 * (int64_t)lab.y) * F;
-        const TA *ss = tab + ((int64_t)it.k[0] + 2 * (int64_t)it.k[1] + lab.z) * F;
-        const int64_t cbase = (it.dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
-        const TS *dq = (const TS *)a.dpack + cbase;
-        const TS *du = dq + (int64_t)F * kChunk;
-        const TS *wq = (WM == 2) ? (const TS *)a.wpack + cbase : nullptr;
-        const TS *wu = (WM == 2) ? wq + (int64_t)F * kChunk : nullptr;
+        const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
+        const gptr<TA> pd = tab + (int64_t)lab_d * F;
+        const gptr<TA> bt = tab + (kd + 2 * (int64_t)lab_t) * F;
+        const gptr<TA> ss = tab + (kd + 2 * kt + lab_s) * F;
+        const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+        const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
+        const gptr<TS> du = dq + (int64_t)F * kChunk;
+        const gptr<TS> wq = (WM == 2) ? as_global((const TS *)a.wpack) + cbase : nullptr;
+        const gptr<TS> wu = (WM == 2) ? wq + (int64_t)F * kChunk : nullptr;
+        const int64_t part_off = it->part_off;
 
         WAcc<TA> A[NW];
         SAcc<TA> S[2];
@@ -156,24 +181,16 @@ __global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
         S[0] = SAcc<TA>{};
         S[1] = SAcc<TA>{};
 
-        // FM is the compile-time band count (kFMax = generic: the runtime F).  A partial unroll
-        // keeps a few bands of loads in flight without hoisting the whole band loop's loads
-        // into registers (that would drop occupancy to one wavefront per SIMD).
-        const int nf = (FM == kFMax) ? F : FM;
-#pragma unroll CS_BAND_UNROLL
-        for (int f = 0; f < nf; ++f) {
-            const int fc = f;
-            const TA d0 = (TA)dq[fc * kChunk];
-            const TA d1 = (TA)du[fc * kChunk];
-            const TA ad = pd[fc] * bt[2 * fc];
-            const TA dt = bt[2 * fc + 1];
-            const TA as = ss[fc];
+        // One band's contribution to M, G (per weight set) and b, h (per Stokes).
+        auto band = [&](const int f, const TA d0, const TA d1, const TA tpd, const TA tbt, const TA dt, const TA as) {
+            const TA ad = tpd * tbt;
             const TA lgd = Band<TA>::ld(B, f);
             const TA lgs = Band<TA>::ls(B, f);
             TA w[2];
             if (WM == 2) {
-                w[0] = (TA)wq[fc * kChunk];
-                w[1] = (TA)wu[fc * kChunk];
+                const int fc = f < F ? f : F - 1;
+                w[0] = f < F ? (TA)wq[fc * kChunk] : (TA)0;
+                w[1] = f < F ? (TA)wu[fc * kChunk] : (TA)0;
             } else {
                 w[0] = Band<TA>::w(B, 0, f);
                 w[1] = Band<TA>::w(B, 1, f);
@@ -218,6 +235,45 @@ __global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
                     c.h3 = fma(was * lgs, dv, c.h3);
                 }
             }
+        };
+        // Bands are consumed in groups of kG.  Per group: issue the SED-table gathers of the
+        // group, then prefetch the next group's Q/U data, then compute.  Vector-memory loads
+        // retire in order, so waiting for the gathers leaves the prefetch in flight, and the
+        // loop is not unrolled so the compiler cannot hoist every load to the top.  Bands past F
+        // read a valid clamped address and carry zero weight.
+        constexpr int kG = CS_BAND_GROUP;
+        TS nq[kG], nu[kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            const int f = j < F ? j : F - 1;
+            nq[j] = dq[f * kChunk];
+            nu[j] = du[f * kChunk];
+        }
+        for (int g0 = 0; g0 < F; g0 += kG) {
+            TS cq[kG], cu[kG];
+            TA tpd[kG], tbt[kG], tdt[kG], tss[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                cq[j] = nq[j];
+                cu[j] = nu[j];
+                const int f = g0 + j < F ? g0 + j : F - 1;
+                tpd[j] = pd[f];
+                tbt[j] = bt[2 * f];
+                tdt[j] = bt[2 * f + 1];
+                tss[j] = ss[f];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (g0 + kG < F) {
+#pragma unroll
+                for (int j = 0; j < kG; ++j) {
+                    const int f = g0 + kG + j < F ? g0 + kG + j : F - 1;
+                    nq[j] = dq[f * kChunk];
+                    nu[j] = du[f * kChunk];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kG; ++j) band(g0 + j, (TA)cq[j], (TA)cu[j], tpd[j], tbt[j], tdt[j], tss[j]);
         }
 
         // a5: FP64 Cholesky of each weight set's M, then per Stokes z = L^-1 b, b^T M^-1 b = z.z,
@@ -294,7 +350,7 @@ __global__ __launch_bounds__(512) void k_pixel(const EvalArgs a) {
         }
         const bool last = (lane == 63) || ((head >> (lane + 1)) & 1ull);
         if (last) {
-            double *o = a.partials + (it.part_off + segbase + segl) * 4;
+            double *o = a.partials + (part_off + segbase + segl) * 4;
             o[0] = fpix;
             o[1] = g1;
             o[2] = g2;
@@ -385,27 +441,21 @@ __global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2log
 // host side
 // ---------------------------------------------------------------------------------------------
 template <typename TS, typename TA, bool GRAD>
-static void launch_pixel_t(int wm, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    if (wm == 0) {
-        if (F == 15)
-            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, 15>), grid, block, 0, s, a);
-        else if (F == 22)
-            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, 22>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, kFMax>), grid, block, 0, s, a);
-    } else if (wm == 1) {
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, kFMax>), grid, block, 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2, kFMax>), grid, block, 0, s, a);
-    }
+static void launch_pixel_t(int wm, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (wm == 0)
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0>), grid, block, 0, s, a);
+    else if (wm == 1)
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2>), grid, block, 0, s, a);
 }
 
 template <typename TS, typename TA>
-static void launch_pixel_g(bool grad, int wm, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+static void launch_pixel_g(bool grad, int wm, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
     if (grad)
-        launch_pixel_t<TS, TA, true>(wm, F, grid, block, s, a);
+        launch_pixel_t<TS, TA, true>(wm, grid, block, s, a);
     else
-        launch_pixel_t<TS, TA, false>(wm, F, grid, block, s, a);
+        launch_pixel_t<TS, TA, false>(wm, grid, block, s, a);
 }
 
 cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
@@ -459,11 +509,11 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
         CSI_HIP(hipEventRecord(e0, s));
     }
     if (mode == CS_FP64)
-        launch_pixel_g<double, double>(want_grad, wm, p->F, grid, block, s, a);
+        launch_pixel_g<double, double>(want_grad, wm, grid, block, s, a);
     else if (mode == CS_FP32_BULK)
-        launch_pixel_g<float, float>(want_grad, wm, p->F, grid, block, s, a);
+        launch_pixel_g<float, float>(want_grad, wm, grid, block, s, a);
     else
-        launch_pixel_g<float, double>(want_grad, wm, p->F, grid, block, s, a);
+        launch_pixel_g<float, double>(want_grad, wm, grid, block, s, a);
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 

@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="kernel-profiling run: only the timed evaluations of one precision")
     ap.add_argument("--precision", default="fp32_bulk", choices=["fp64", "fp32_bulk", "fp32_store"])
+    ap.add_argument("--shared-segments", type=int, default=None, choices=[0, 1],
+                    help="profiling run: force the per-pixel (0) or segment-shared (1) schedule")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="HBM counter calibration: time a plain device copy of this many bytes and exit")
     args = ap.parse_args()
@@ -136,6 +138,8 @@ def main():
 
     if args.profile:
         prob = cs.Problem.from_sky(sky, args.precision)
+        if args.shared_segments is not None:
+            prob.set_schedule(4, 0, 1, args.shared_segments)
         wall, kms, nl, _ = time_eval(prob, x, args.steps, args.warmup)
         ab = algorithmic_bytes(prob, sky, 8 if args.precision == "fp64" else 4)
         print(json.dumps({"precision": args.precision, "ms_per_step": wall / args.steps * 1e3,

@@ -48,8 +48,11 @@ typedef enum {
 
 /* Working precision of the per-pixel data stream (d and per-pixel N^-1).
  *   CS_FP64       : FP64 storage, FP64 frequency accumulation, FP64 solve and reductions.
- *   CS_FP32_BULK  : FP32 storage, FP32 frequency accumulation (M, b and the adjoint sums),
- *                   FP64 3x3 Cholesky solve, FP64 compensated per-cluster reductions.
+ *   CS_FP32_BULK  : FP32 storage, FP32 frequency accumulation of every sum that involves the
+ *                   data (A^T N^-1 d and its adjoint counterparts), FP64 3x3 Cholesky solve,
+ *                   FP64 compensated per-cluster reductions.  The data-free sums (A^T N^-1 A and
+ *                   the adjoint sums A^T N^-1 dA) are formed in FP64 once per segment when the
+ *                   schedule shares them (cs_schedule.shared_segments), else in FP32 per pixel.
  *   CS_FP32_STORE : FP32 storage, FP64 accumulation, solve and reductions.  */
 typedef enum { CS_FP64 = 0, CS_FP32_BULK = 1, CS_FP32_STORE = 2 } cs_precision;
 
@@ -169,14 +172,20 @@ typedef struct {
     int32_t blocks_per_cu;   /* 0 = one 64-pixel unit per wavefront (no grid-stride loop);
                                 n > 0 = persistent grid of n * 256 workgroups              */
     int32_t xcd_remap;       /* 1 = give each of the 8 XCDs a contiguous range of units    */
+    int32_t shared_segments; /* 1 = form A^T N^-1 A, its Cholesky factor and the adjoint
+                                sums once per segment (constant-label run) in LDS and share
+                                them across its pixels (band weights shared by Q and U
+                                only); 0 = every pixel forms its own                       */
 } cs_schedule;
 
 cs_status cs_problem_get_schedule(const cs_problem *prob, cs_schedule *sched);
 cs_status cs_problem_set_schedule(cs_problem *prob, const cs_schedule *sched);
 
 /* Times every candidate schedule on cs_likelihood_grad at x (reps evaluations each, HIP
- * events on the stream) and keeps the fastest; candidates producing results that differ
- * from the default schedule's are rejected.  grad / neg2logL are scratch outputs.  Writes
+ * events on the stream) and keeps the fastest.  Candidates that only move work between
+ * wavefronts must reproduce the current schedule's F bit for bit; candidates that change
+ * shared_segments (a different rounding order) must agree to 1e-11 relative (1e-6 for
+ * CS_FP32_BULK); others are rejected.  grad / neg2logL are scratch outputs.  Writes
  * the chosen schedule to *best (nullable).  Synchronises the stream. */
 cs_status cs_problem_autotune(cs_problem *prob, const double *x, double *neg2logL, double *grad,
                               int32_t reps, cs_schedule *best, void *stream);

@@ -49,7 +49,8 @@ class OptimOpts(C.Structure):
 
 
 class Schedule(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("xcd_remap", C.c_int32)]
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("xcd_remap", C.c_int32),
+                ("shared_segments", C.c_int32)]
 
 
 _lib = None
@@ -288,8 +289,8 @@ class Problem:
         _check(load().cs_problem_get_schedule(self._h, C.byref(s)), "cs_problem_get_schedule")
         return s
 
-    def set_schedule(self, waves_per_block=4, blocks_per_cu=0, xcd_remap=1):
-        s = Schedule(waves_per_block, blocks_per_cu, xcd_remap)
+    def set_schedule(self, waves_per_block=4, blocks_per_cu=0, xcd_remap=1, shared_segments=1):
+        s = Schedule(waves_per_block, blocks_per_cu, xcd_remap, shared_segments)
         _check(load().cs_problem_set_schedule(self._h, C.byref(s)), "cs_problem_set_schedule")
 
     def autotune(self, x, reps: int = 3) -> Schedule:

@@ -74,6 +74,8 @@ static void carve(cs_problem *p) {
     w.wpack = take(p->nmode == CS_NINV_PIXEL ? elem * 2 * (size_t)p->F * kChunk * w.nchunk_max * B : 0);
     w.tables = take(sizeof(double) * (size_t)p->F * (size_t)p->taboff[p->B]);
     w.partials = take(sizeof(double) * 4 * w.p64 * B);
+    w.records = take(sizeof(double) * 16 * w.p64 * B);
+    w.segoff = take(sizeof(int64_t) * (B + 1));
     w.istatus = take(sizeof(int32_t) * B);
     w.total = off;
 }
@@ -296,6 +298,9 @@ cs_status cs_problem_prepare(cs_problem *p, void *workspace, size_t bytes, void 
         for (int c = 0; c < L.nchunks; ++c) units.push_back(make_int2(b, c));
     }
     p->nunits = (int64_t)units.size();
+    p->segoff.assign(p->B + 1, 0);
+    for (int b = 0; b < p->B; ++b) p->segoff[b + 1] = p->segoff[b] + p->layouts[p->items[b].layout].nseg;
+    CSI_HIP(hipMemcpyAsync(base + w.segoff, p->segoff.data(), sizeof(int64_t) * (p->B + 1), hipMemcpyHostToDevice, s));
     CSI_HIP(hipMemcpyAsync(base + w.layouts, p->layouts.data(), sizeof(LayoutDev) * p->L, hipMemcpyHostToDevice, s));
     if (!units.empty())
         CSI_HIP(hipMemcpyAsync(base + w.units, units.data(), sizeof(int2) * units.size(), hipMemcpyHostToDevice, s));
@@ -394,7 +399,7 @@ cs_status cs_problem_set_schedule(cs_problem *p, const cs_schedule *s) {
     if (!p || !s) return invalid("null argument");
     const int w = s->waves_per_block;
     if (!(w == 1 || w == 2 || w == 4 || w == 8) || s->blocks_per_cu < 0 || s->blocks_per_cu > 64 ||
-        (s->xcd_remap != 0 && s->xcd_remap != 1))
+        (s->xcd_remap != 0 && s->xcd_remap != 1) || (s->shared_segments != 0 && s->shared_segments != 1))
         return invalid("bad schedule");
     p->sched = *s;
     return CS_OK;
@@ -422,31 +427,40 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
     cs_schedule bestsch = keep;
     float bestms = 1e30f;
     const int waves[4] = {1, 2, 4, 8};
-    const int bpc[4] = {0, 2, 4, 8};
-    for (int wi = 0; wi < 4 && rc == CS_OK; ++wi)
-        for (int bi = 0; bi < 4 && rc == CS_OK; ++bi)
-            for (int xr = 0; xr < 2 && rc == CS_OK; ++xr) {
-                p->sched = cs_schedule{waves[wi], bpc[bi], xr};
-                rc = launch_eval(p, x, nullptr, neg2logl, grad, nullptr, nullptr, true, p->prec, s);  // warm-up
-                if (rc != CS_OK) break;
-                if (hipEventRecord(e0, s) != hipSuccess) rc = CS_E_HIP;
-                for (int r = 0; r < reps && rc == CS_OK; ++r)
-                    rc = launch_eval(p, x, nullptr, neg2logl, grad, nullptr, nullptr, true, p->prec, s);
-                if (rc != CS_OK) break;
-                float ms = 0.f;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
-                    hipMemcpy(got.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost) != hipSuccess) {
-                    rc = CS_E_HIP;
-                    break;
+    const int bpc[3] = {0, 2, 4};
+    const double cross_tol = p->prec == CS_FP32_BULK ? 1e-6 : 1e-11;
+    for (int sh = 0; sh < 2 && rc == CS_OK; ++sh)
+        for (int wi = 0; wi < 4 && rc == CS_OK; ++wi)
+            for (int bi = 0; bi < 3 && rc == CS_OK; ++bi)
+                for (int xr = 0; xr < 2 && rc == CS_OK; ++xr) {
+                    p->sched = cs_schedule{waves[wi], bpc[bi], xr, sh};
+                    rc = launch_eval(p, x, nullptr, neg2logl, grad, nullptr, nullptr, true, p->prec, s);  // warm-up
+                    if (rc != CS_OK) break;
+                    if (hipEventRecord(e0, s) != hipSuccess) rc = CS_E_HIP;
+                    for (int r = 0; r < reps && rc == CS_OK; ++r)
+                        rc = launch_eval(p, x, nullptr, neg2logl, grad, nullptr, nullptr, true, p->prec, s);
+                    if (rc != CS_OK) break;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+                        hipMemcpy(got.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost) != hipSuccess) {
+                        rc = CS_E_HIP;
+                        break;
+                    }
+                    bool agree = true;
+                    if (sh == keep.shared_segments) {
+                        // same arithmetic, work only moved between wavefronts: bit-identical
+                        agree = std::memcmp(got.data(), ref.data(), sizeof(double) * p->B) == 0;
+                    } else {
+                        for (int b = 0; b < p->B; ++b)
+                            if (!(std::fabs(got[b] - ref[b]) <= cross_tol * std::fabs(ref[b]))) agree = false;
+                    }
+                    if (!agree) continue;
+                    if (ms < bestms) {
+                        bestms = ms;
+                        bestsch = p->sched;
+                    }
                 }
-                // schedules only move work between wavefronts: results must be bit-identical
-                if (std::memcmp(got.data(), ref.data(), sizeof(double) * p->B) != 0) continue;
-                if (ms < bestms) {
-                    bestms = ms;
-                    bestsch = p->sched;
-                }
-            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->sched = (rc == CS_OK) ? bestsch : keep;

@@ -130,28 +130,146 @@ __device__ __forceinline__ uint64_t lanemask_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
 
+// Band loop of one pixel: calls band(f, d_Q, d_U, PD, BT, DT, SS) for f = 0..F-1.
+// FM > 0 (compile-time band count): the pixel's whole Q/U data column is requested first (one
+// HBM round trip per wavefront), then the SED-table gathers run one group of kG bands ahead of
+// the arithmetic.  Vector-memory loads retire in order, so a wait for a gather never waits for
+// a data load issued after it.  Scheduling barriers keep the compiler from hoisting the later
+// gathers to the top.  FM == 0 (any F): groups of kG bands with the next group's data prefetched
+// behind the current group's gathers.  Bands past F read a clamped address and are not used.
+template <int FM, int kG, typename TS, typename TA, typename BandFn>
+__device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const gptr<TS> du, const gptr<TA> pd,
+                                          const gptr<TA> bt, const gptr<TA> ss, BandFn &&band) {
+    if constexpr (FM > 0) {
+        constexpr int NG = (FM + kG - 1) / kG;
+        TS vq[FM], vu[FM];
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            vq[f] = dq[f * kChunk];
+            vu[f] = du[f * kChunk];
+        }
+        TA tp[2][kG], tb[2][kG], tt[2][kG], ts[2][kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            const int f = j < FM ? j : FM - 1;
+            tp[0][j] = pd[f];
+            tb[0][j] = bt[2 * f];
+            tt[0][j] = bt[2 * f + 1];
+            ts[0][j] = ss[f];
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (g + 1 < NG) {
+                const int nb = (g + 1) & 1;
+#pragma unroll
+                for (int j = 0; j < kG; ++j) {
+                    const int f = (g + 1) * kG + j < FM ? (g + 1) * kG + j : FM - 1;
+                    tp[nb][j] = pd[f];
+                    tb[nb][j] = bt[2 * f];
+                    tt[nb][j] = bt[2 * f + 1];
+                    ts[nb][j] = ss[f];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const int cb = g & 1;
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int f = g * kG + j;
+                if (f < FM) band(f, (TA)vq[f], (TA)vu[f], tp[cb][j], tb[cb][j], tt[cb][j], ts[cb][j]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        TS nq[kG], nu[kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            const int f = j < F ? j : F - 1;
+            nq[j] = dq[f * kChunk];
+            nu[j] = du[f * kChunk];
+        }
+        for (int g0 = 0; g0 < F; g0 += kG) {
+            TS cq[kG], cu[kG];
+            TA tpd[kG], tbt[kG], tdt[kG], tss[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                cq[j] = nq[j];
+                cu[j] = nu[j];
+                const int f = g0 + j < F ? g0 + j : F - 1;
+                tpd[j] = pd[f];
+                tbt[j] = bt[2 * f];
+                tdt[j] = bt[2 * f + 1];
+                tss[j] = ss[f];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (g0 + kG < F) {
+#pragma unroll
+                for (int j = 0; j < kG; ++j) {
+                    const int f = g0 + kG + j < F ? g0 + kG + j : F - 1;
+                    nq[j] = dq[f * kChunk];
+                    nu[j] = du[f * kChunk];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (g0 + j < F) band(g0 + j, (TA)cq[j], (TA)cu[j], tpd[j], tbt[j], tdt[j], tss[j]);
+        }
+    }
+}
+
+// a7 (first level): inclusive scan inside each constant-label run of the wavefront; the run's
+// last lane holds the run total and writes the segment's (f, dF/dbeta_d, dF/dT_d, dF/dbeta_s).
+template <bool GRAD>
+__device__ __forceinline__ void seg_reduce_write(uint64_t head, int lane, double fpix, double g1, double g2,
+                                                 double g3, double *out) {
+    const int start = 63 - __clzll(head & lanemask_le(lane));
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double of = __shfl_up(fpix, off, 64);
+        double o1 = 0, o2 = 0, o3 = 0;
+        if (GRAD) {
+            o1 = __shfl_up(g1, off, 64);
+            o2 = __shfl_up(g2, off, 64);
+            o3 = __shfl_up(g3, off, 64);
+        }
+        if (lane - off >= start) {
+            fpix += of;
+            if (GRAD) {
+                g1 += o1;
+                g2 += o2;
+                g3 += o3;
+            }
+        }
+    }
+    const bool last = (lane == 63) || ((head >> (lane + 1)) & 1ull);
+    if (last) {
+        out[0] = fpix;
+        out[1] = GRAD ? g1 : 0.0;
+        out[2] = GRAD ? g2 : 0.0;
+        out[3] = GRAD ? g3 : 0.0;
+    }
+}
+
 // WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
-template <typename TS, typename TA, bool GRAD, int WM>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PER_EU))) void k_pixel(const EvalArgs a) {
-    constexpr int NW = (WM == 0) ? 1 : 2;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = a.waves_per_block;
+__device__ __forceinline__ int64_t logical_block(int xcd_remap) {
     const int64_t nb = gridDim.x;
     int64_t lb = blockIdx.x;
-    if (a.xcd_remap) {  // blocks are dealt round-robin to the XCDs: give each XCD a contiguous range
+    if (xcd_remap) {  // blocks are dealt round-robin to the XCDs: give each XCD a contiguous range
         const int64_t x = lb % kNumXcd, i = lb / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
         lb = x * q + (x < r ? x : r) + i;
     }
+    return lb;
+}
+
+// One 64-pixel work unit, every per-pixel sum formed by its own lane.
+template <typename TS, typename TA, bool GRAD, int WM, int FM>
+__device__ __forceinline__ void unit_pixel(const EvalArgs &a, const int item, const int chunk, const int lane) {
+    constexpr int NW = (WM == 0) ? 1 : 2;
     const cptr<BandDev> B = as_const(a.band);
     const int F = a.nfreq;
-    const cptr<int> units = as_const((const int *)a.units);
     const cptr<ItemDev> items = as_const(a.items);
     const cptr<LayoutDev> layouts = as_const(a.layouts);
-    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
-        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
-        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
-        if (a.active && !as_const(a.active)[item]) continue;
+    {
         const cptr<ItemDev> it = items + item;
         const cptr<LayoutDev> L = layouts + it->layout;
         const uint64_t head = as_const(L->head)[chunk];
@@ -236,45 +354,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
                 }
             }
         };
-        // Bands are consumed in groups of kG.  Per group: issue the SED-table gathers of the
-        // group, then prefetch the next group's Q/U data, then compute.  Vector-memory loads
-        // retire in order, so waiting for the gathers leaves the prefetch in flight, and the
-        // loop is not unrolled so the compiler cannot hoist every load to the top.  Bands past F
-        // read a valid clamped address and carry zero weight.
-        constexpr int kG = CS_BAND_GROUP;
-        TS nq[kG], nu[kG];
-#pragma unroll
-        for (int j = 0; j < kG; ++j) {
-            const int f = j < F ? j : F - 1;
-            nq[j] = dq[f * kChunk];
-            nu[j] = du[f * kChunk];
-        }
-        for (int g0 = 0; g0 < F; g0 += kG) {
-            TS cq[kG], cu[kG];
-            TA tpd[kG], tbt[kG], tdt[kG], tss[kG];
-#pragma unroll
-            for (int j = 0; j < kG; ++j) {
-                cq[j] = nq[j];
-                cu[j] = nu[j];
-                const int f = g0 + j < F ? g0 + j : F - 1;
-                tpd[j] = pd[f];
-                tbt[j] = bt[2 * f];
-                tdt[j] = bt[2 * f + 1];
-                tss[j] = ss[f];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            if (g0 + kG < F) {
-#pragma unroll
-                for (int j = 0; j < kG; ++j) {
-                    const int f = g0 + kG + j < F ? g0 + kG + j : F - 1;
-                    nq[j] = dq[f * kChunk];
-                    nu[j] = du[f * kChunk];
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int j = 0; j < kG; ++j) band(g0 + j, (TA)cq[j], (TA)cu[j], tpd[j], tbt[j], tdt[j], tss[j]);
-        }
+        band_loop<FM, CS_BAND_GROUP, TS, TA>(F, dq, du, pd, bt, ss, band);
 
         // a5: FP64 Cholesky of each weight set's M, then per Stokes z = L^-1 b, b^T M^-1 b = z.z,
         // s_hat = L^-T z; a6: gradient from h and G.
@@ -327,35 +407,231 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
         const uint64_t bad = __ballot(valid && !ok);
         if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
 
-        // a7 (first level): inclusive scan inside each constant-label run of the wavefront;
-        // the run's last lane holds the run total.
-        const int start = 63 - __clzll(head & lanemask_le(lane));
+        seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (part_off + segbase + segl) * 4);
+    }
+}
+
+template <typename TS, typename TA, bool GRAD, int WM, int FM>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PER_EU))) void k_pixel(const EvalArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = a.waves_per_block;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const cptr<int> units = as_const((const int *)a.units);
+    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
+        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
+        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
+        if (a.active && !as_const(a.active)[item]) continue;
+        unit_pixel<TS, TA, GRAD, WM, FM>(a, item, chunk, lane);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Segment-shared variant (band weights shared by Q and U).  M = A^T N^-1 A and the adjoint sums
+// G_jk depend only on a pixel's three labels, so they are identical for every pixel of a segment.
+// A pre-pass with one thread per (item, segment) forms M and G in FP64 and the Cholesky factor of
+// M into a 128-byte record; the pixel kernel then streams the data and forms only the
+// data-dependent sums b and h per pixel, reading its segment's record (shared by the segment's
+// lanes through the cache).
+// ---------------------------------------------------------------------------------------------
+struct SegRec {  // Cholesky factor of M (inverse diagonal), G_jk, and a positive-definite flag
+    double i00, l10, l20, i11, l21, i22;
+    double g01, g02, g03, g11, g12, g13, g21, g22, g23;
+    double ok;
+};
+
+template <typename TA>
+__device__ __forceinline__ void segment_record(const EvalArgs &a, const int item, const int seg, SegRec *out) {
+    const cptr<BandDev> B = as_const(a.band);
+    const int F = a.nfreq;
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
+    const gptr<int> labp = as_global((const int *)L->seg_lab) + 4 * (int64_t)seg;
+    const int64_t kd = it->k[0], kt = it->k[1];
+    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
+    const gptr<TA> pd = tab + (int64_t)labp[0] * F;
+    const gptr<TA> bt = tab + (kd + 2 * (int64_t)labp[1]) * F;
+    const gptr<TA> ss = tab + (kd + 2 * kt + labp[2]) * F;
+    double m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+    double g01 = 0, g02 = 0, g03 = 0, g11 = 0, g12 = 0, g13 = 0, g21 = 0, g22 = 0, g23 = 0;
+#pragma unroll 2
+    for (int f = 0; f < F; ++f) {
+        const double ad = (double)pd[f] * (double)bt[2 * f];
+        const double dt = (double)bt[2 * f + 1];
+        const double as = (double)ss[f];
+        const double w = B->w[0][f];
+        const double wad = w * ad, was = w * as;
+        m01 += wad;
+        m02 += was;
+        m11 = fma(wad, ad, m11);
+        m12 = fma(wad, as, m12);
+        m22 = fma(was, as, m22);
+        const double c1 = wad * B->ld[f], c2 = wad * dt, c3 = was * B->ls[f];
+        g01 += c1;
+        g02 += c2;
+        g03 += c3;
+        g11 = fma(c1, ad, g11);
+        g12 = fma(c2, ad, g12);
+        g13 = fma(c3, ad, g13);
+        g21 = fma(c1, as, g21);
+        g22 = fma(c2, as, g22);
+        g23 = fma(c3, as, g23);
+    }
+    const double m00 = B->wsum[0];
+    const double l00 = sqrt(m00);
+    const double i00 = 1.0 / l00;
+    const double l10 = m01 * i00, l20 = m02 * i00;
+    const double p1 = m11 - l10 * l10;
+    const double i11 = 1.0 / sqrt(p1);
+    const double l21 = (m12 - l20 * l10) * i11;
+    const double p2 = m22 - l20 * l20 - l21 * l21;
+    const double i22 = 1.0 / sqrt(p2);
+    SegRec r;
+    r.i00 = i00;
+    r.l10 = l10;
+    r.l20 = l20;
+    r.i11 = i11;
+    r.l21 = l21;
+    r.i22 = i22;
+    r.g01 = g01;
+    r.g02 = g02;
+    r.g03 = g03;
+    r.g11 = g11;
+    r.g12 = g12;
+    r.g13 = g13;
+    r.g21 = g21;
+    r.g22 = g22;
+    r.g23 = g23;
+    r.ok = (m00 > 0.0 && p1 > 0.0 && p2 > 0.0) ? 1.0 : 0.0;
+    *out = r;
+}
+
+template <typename TS, typename TA, bool GRAD, int FM>
+__device__ __forceinline__ void unit_seg(const EvalArgs &a, const int item, const int chunk, const int lane,
+                                         const SegRec *recs) {
+    const cptr<BandDev> B = as_const(a.band);
+    const int F = a.nfreq;
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
+    const uint64_t head = as_const(L->head)[chunk];
+    const int segbase = as_const(L->seg_base)[chunk];
+    const int nvalid = L->n_incl - chunk * kChunk;
+    const bool valid = lane < nvalid;
+    const int segl = __popcll(head & lanemask_le(lane)) - 1;
+    const gptr<int> labp = as_global((const int *)L->seg_lab) + 4 * (int64_t)(segbase + segl);
+    const int lab_d = labp[0], lab_t = labp[1], lab_s = labp[2];
+    const int64_t kd = it->k[0], kt = it->k[1];
+    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
+    const gptr<TA> pd = tab + (int64_t)lab_d * F;
+    const gptr<TA> bt = tab + (kd + 2 * (int64_t)lab_t) * F;
+    const gptr<TA> ss = tab + (kd + 2 * kt + lab_s) * F;
+    const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+    const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
+    const gptr<TS> du = dq + (int64_t)F * kChunk;
+
+    SAcc<TA> S[2];
+    S[0] = SAcc<TA>{};
+    S[1] = SAcc<TA>{};
+    auto band = [&](const int f, const TA d0, const TA d1, const TA tpd, const TA tbt, const TA dt, const TA as) {
+        const TA w = Band<TA>::w(B, 0, f);
+        const TA cb1 = w * (tpd * tbt), cb2 = w * as;
+        const TA ch1 = cb1 * Band<TA>::ld(B, f), ch2 = cb1 * dt, ch3 = cb2 * Band<TA>::ls(B, f);
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double of = __shfl_up(fpix, off, 64);
-            double o1 = 0, o2 = 0, o3 = 0;
+        for (int s = 0; s < 2; ++s) {
+            const TA dv = s ? d1 : d0;
+            SAcc<TA> &c = S[s];
+            c.b0 = fma(w, dv, c.b0);
+            c.b1 = fma(cb1, dv, c.b1);
+            c.b2 = fma(cb2, dv, c.b2);
             if (GRAD) {
-                o1 = __shfl_up(g1, off, 64);
-                o2 = __shfl_up(g2, off, 64);
-                o3 = __shfl_up(g3, off, 64);
-            }
-            if (lane - off >= start) {
-                fpix += of;
-                if (GRAD) {
-                    g1 += o1;
-                    g2 += o2;
-                    g3 += o3;
-                }
+                c.h1 = fma(ch1, dv, c.h1);
+                c.h2 = fma(ch2, dv, c.h2);
+                c.h3 = fma(ch3, dv, c.h3);
             }
         }
-        const bool last = (lane == 63) || ((head >> (lane + 1)) & 1ull);
-        if (last) {
-            double *o = a.partials + (part_off + segbase + segl) * 4;
-            o[0] = fpix;
-            o[1] = g1;
-            o[2] = g2;
-            o[3] = g3;
+    };
+    band_loop<FM, CS_BAND_GROUP, TS, TA>(F, dq, du, pd, bt, ss, band);
+
+    // the segment's record (16 doubles, the same address for every lane of the segment)
+    const gptr<double> rp = as_global((const double *)recs) + 16 * (int64_t)segl;
+    SegRec R;
+    R.i00 = rp[0];
+    R.l10 = rp[1];
+    R.l20 = rp[2];
+    R.i11 = rp[3];
+    R.l21 = rp[4];
+    R.i22 = rp[5];
+    R.g01 = rp[6];
+    R.g02 = rp[7];
+    R.g03 = rp[8];
+    R.g11 = rp[9];
+    R.g12 = rp[10];
+    R.g13 = rp[11];
+    R.g21 = rp[12];
+    R.g22 = rp[13];
+    R.g23 = rp[14];
+    R.ok = rp[15];
+    const bool ok = R.ok != 0.0;
+    double fpix = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const SAcc<TA> &q = S[s];
+        const double z0 = (double)q.b0 * R.i00;
+        const double z1 = ((double)q.b1 - R.l10 * z0) * R.i11;
+        const double z2 = ((double)q.b2 - R.l20 * z0 - R.l21 * z1) * R.i22;
+        fpix -= z0 * z0 + z1 * z1 + z2 * z2;
+        if (GRAD) {
+            const double s2 = z2 * R.i22;
+            const double s1 = (z1 - R.l21 * s2) * R.i11;
+            const double s0 = (z0 - R.l10 * s1 - R.l20 * s2) * R.i00;
+            const double e1 = (double)q.h1 - (s0 * R.g01 + s1 * R.g11 + s2 * R.g21);
+            const double e2 = (double)q.h2 - (s0 * R.g02 + s1 * R.g12 + s2 * R.g22);
+            const double e3 = (double)q.h3 - (s0 * R.g03 + s1 * R.g13 + s2 * R.g23);
+            g1 -= 2.0 * s1 * e1;
+            g2 -= 2.0 * s1 * e2;
+            g3 -= 2.0 * s2 * e3;
         }
+    }
+    if (!valid) {
+        fpix = 0.0;
+        g1 = g2 = g3 = 0.0;
+    } else if (!ok) {
+        fpix = g1 = g2 = g3 = __builtin_nan("");
+    }
+    const uint64_t bad = __ballot(valid && !ok);
+    if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
+    seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (it->part_off + segbase + segl) * 4);
+}
+
+// Pre-pass: one thread per (item, segment) writes the segment's record.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_seg_records(const EvalArgs a, const int64_t *segoff) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= segoff[a.nitems]) return;
+    const int item = find_item(segoff, a.nitems, g);
+    if (a.active && !a.active[item]) return;
+    const int seg = (int)(g - segoff[item]);
+    SegRec *out = (SegRec *)a.records + (as_const(a.items) + item)->part_off + seg;
+    segment_record<TA>(a, item, seg, out);
+}
+
+template <typename TS, typename TA, bool GRAD, int FM>
+__global__ __launch_bounds__(512) void k_pixel_seg(const EvalArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = a.waves_per_block;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const cptr<int> units = as_const((const int *)a.units);
+    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
+        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
+        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
+        if (a.active && !as_const(a.active)[item]) continue;
+        const cptr<ItemDev> it = as_const(a.items) + item;
+        const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
+        const int segbase = as_const(L->seg_base)[chunk];
+        unit_seg<TS, TA, GRAD, FM>(a, item, chunk, lane, (const SegRec *)a.records + it->part_off + segbase);
     }
 }
 
@@ -440,22 +716,34 @@ __global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2log
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
-template <typename TS, typename TA, bool GRAD>
-static void launch_pixel_t(int wm, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    if (wm == 0)
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0>), grid, block, 0, s, a);
+template <typename TS, typename TA, bool GRAD, int FM>
+static void launch_pixel_f(int wm, bool shared, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (wm == 0 && shared)
+        hipLaunchKernelGGL((k_pixel_seg<TS, TA, GRAD, FM>), grid, block, 0, s, a);
+    else if (wm == 0)
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, FM>), grid, block, 0, s, a);
     else if (wm == 1)
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, 0>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2, 0>), grid, block, 0, s, a);
+}
+
+// The compile-time band-count instantiation (FM > 0, whole data column requested up front) needs
+// more registers than it saves in latency on gfx950 (measured: slower for every precision at
+// F = 22); every band count runs the grouped runtime-F loop.
+template <typename TS, typename TA, bool GRAD>
+static void launch_pixel_t(int wm, bool shared, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    (void)F;
+    launch_pixel_f<TS, TA, GRAD, 0>(wm, shared, grid, block, s, a);
 }
 
 template <typename TS, typename TA>
-static void launch_pixel_g(bool grad, int wm, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+static void launch_pixel_g(bool grad, int wm, bool shared, int F, dim3 grid, dim3 block, hipStream_t s,
+                           const EvalArgs &a) {
     if (grad)
-        launch_pixel_t<TS, TA, true>(wm, grid, block, s, a);
+        launch_pixel_t<TS, TA, true>(wm, shared, F, grid, block, s, a);
     else
-        launch_pixel_t<TS, TA, false>(wm, grid, block, s, a);
+        launch_pixel_t<TS, TA, false>(wm, shared, F, grid, block, s, a);
 }
 
 cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
@@ -471,6 +759,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     a.tables = p->wsp + w.tables;
     a.band = (const BandDev *)(p->wsp + w.band);
     a.partials = (double *)(p->wsp + w.partials);
+    a.records = p->wsp + w.records;
     a.istatus = (int32_t *)(p->wsp + w.istatus);
     a.active = active;
     a.x = x;
@@ -495,6 +784,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     if (nblocks < 1) nblocks = 1;
     const dim3 grid((unsigned)nblocks), block((unsigned)(64 * wpb));
     const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
+    const bool shared = p->sched.shared_segments != 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p->timing) {
         if (p->events_used == p->events.size()) {
@@ -508,12 +798,25 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
         ++p->events_used;
         CSI_HIP(hipEventRecord(e0, s));
     }
+    if (wm == 0 && shared) {
+        const int64_t nsegs = p->segoff[p->B];
+        const int64_t *segoff_dev = (const int64_t *)(p->wsp + w.segoff);
+        if (nsegs > 0) {
+            if (t32)
+                hipLaunchKernelGGL(k_seg_records<float>, dim3((unsigned)((nsegs + 255) / 256)), dim3(256), 0, s, a,
+                                   segoff_dev);
+            else
+                hipLaunchKernelGGL(k_seg_records<double>, dim3((unsigned)((nsegs + 255) / 256)), dim3(256), 0, s, a,
+                                   segoff_dev);
+            CSI_HIP(hipGetLastError());
+        }
+    }
     if (mode == CS_FP64)
-        launch_pixel_g<double, double>(want_grad, wm, grid, block, s, a);
+        launch_pixel_g<double, double>(want_grad, wm, shared, p->F, grid, block, s, a);
     else if (mode == CS_FP32_BULK)
-        launch_pixel_g<float, float>(want_grad, wm, grid, block, s, a);
+        launch_pixel_g<float, float>(want_grad, wm, shared, p->F, grid, block, s, a);
     else
-        launch_pixel_g<float, double>(want_grad, wm, grid, block, s, a);
+        launch_pixel_g<float, double>(want_grad, wm, shared, p->F, grid, block, s, a);
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 

@@ -70,6 +70,7 @@ struct EvalArgs {
     void *tables;        // per item: PD [K_d][F], BTDT [K_T][F][2], SS [K_s][F]
     const BandDev *band;
     double *partials;    // [segment][4]: f, dF/dbeta_d, dF/dT_d, dF/dbeta_s
+    void *records;       // [segment] 128-byte records of the segment-shared path
     int32_t *istatus;    // [B] status bits of the current evaluation
     const int32_t *active;  // nullable [B]: 0 = skip item (converged optimiser items)
     const double *x;     // packed parameters
@@ -82,7 +83,7 @@ struct EvalArgs {
 // Workspace regions (byte offsets, 256-aligned), see carve_workspace().
 struct WsLayout {
     size_t band, items, layouts, units, keys, order, head, seg_base, seg_lab, seg_perm, seg_off,
-        counts, dpack, wpack, tables, partials, istatus, total;
+        counts, dpack, wpack, tables, partials, records, segoff, istatus, total;
     size_t keys_stride, p64, nchunk_max, np2, kmax[3];
 };
 
@@ -110,6 +111,7 @@ struct cs_problem {
     int key_bits[4] = {0, 0, 0, 0};
     std::vector<int64_t> xoff;     // [B+1]
     std::vector<int64_t> taboff;   // [B+1] table rows
+    std::vector<int64_t> segoff;   // [B+1] segments of the items (after prepare)
     csi::WsLayout ws;
     char *wsp = nullptr;
     int device = 0;
@@ -118,7 +120,7 @@ struct cs_problem {
     std::vector<csi::ItemDev> items;
     std::vector<csi::LayoutDev> layouts;
     int64_t nunits = 0;
-    cs_schedule sched{4, 0, 1};
+    cs_schedule sched{4, 0, 1, 1};
     // kernel timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

@@ -246,18 +246,24 @@ __global__ __launch_bounds__(256) void k_seg_csr(const LayoutDev *lays, int j, i
     if (i <= k) L.seg_off[j][i] = (i == k) ? (int32_t)n : (int32_t)lower_bound_keys(L.keys, n, (uint64_t)i << bp);
 }
 
-// pixel keys (l_j, p) of one layout for the exported per-labelling pixel CSR
-__global__ __launch_bounds__(256) void k_pixel_keys(const LayoutDev *lays, int lay, int j, int32_t npix,
-                                                    int64_t np2, int bp) {
+// pixel keys (l_j, p) of one layout for the exported per-labelling pixel CSR, rebuilt from the
+// prepared order and segment triples (the caller's label array is not read again)
+__global__ __launch_bounds__(64) void k_pixel_keys(const LayoutDev *lays, int lay, int j, int64_t np2, int bp) {
     const LayoutDev L = lays[lay];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np2) return;
+    const int64_t chunk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t slot = chunk * kChunk + lane;
+    if (slot >= np2) return;
     uint64_t key = kInvalid;
-    if (i < npix) {
-        const int32_t l0 = L.labels[i];
-        if (l0 >= 0) key = ((uint64_t)L.labels[j * (int64_t)npix + i] << bp) | (uint64_t)i;
+    if (slot < L.n_incl) {
+        const uint64_t mask = L.head[chunk];
+        const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int seg = L.seg_base[chunk] + __popcll(mask & le) - 1;
+        const int4 v = L.seg_lab[seg];
+        const int lab = j == 0 ? v.x : (j == 1 ? v.y : v.z);
+        key = ((uint64_t)lab << bp) | (uint64_t)L.order[slot];
     }
-    L.keys[i] = key;
+    L.keys[slot] = key;
 }
 
 // 5. gather one item's d (and per-pixel N^-1) into [chunk][2][F][64] in working precision
@@ -361,7 +367,7 @@ cs_status export_segments(cs_problem *p, int32_t item, int32_t j, int32_t *perm,
     const int lay = p->items[item].layout;
     const int64_t np2 = (int64_t)w.np2;
     const int bp = bits_for(p->P);
-    hipLaunchKernelGGL(k_pixel_keys, dim3((unsigned)((np2 + 255) / 256)), dim3(256), 0, s, dl, lay, j, p->P, np2, bp);
+    hipLaunchKernelGGL(k_pixel_keys, dim3((unsigned)(np2 / kChunk)), dim3(kChunk), 0, s, dl, lay, j, np2, bp);
     CSI_HIP(hipGetLastError());
     uint64_t *keys = (uint64_t *)(p->wsp + w.keys) + (int64_t)lay * (int64_t)w.keys_stride;
     cs_status st = bitonic_sort(keys, 0, np2, 1, nullptr, s);

@@ -87,13 +87,24 @@ def test_fp64_workload2_full():
     _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
 
 
-@pytest.mark.parametrize("precision", ["fp32_bulk", "fp32_store"])
-def test_fp32_paths_workload2(precision):
+@pytest.mark.parametrize("shared", [1, 0])
+@pytest.mark.parametrize("precision", ["fp32_bulk", "fp32_store", "fp64"])
+def test_precisions_and_sharing_workload2(precision, shared):
     sky = skygen.make_config(2, nitems=4)
-    _log(f"{precision} workload 2")
+    _log(f"{precision} shared_segments={shared} workload 2")
     prob = cs.Problem.from_sky(sky, precision)
+    prob.set_schedule(4, 0, 1, shared)
     ef, eg, ec = compare(sky, prob, precision)
     _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
+
+
+def test_segment_sharing_ragged_many_segments():
+    # ragged configurations where many chunks hold one-pixel segments
+    sky = skygen.make_config(4, nitems=3, kmax4=(3000, 500, 1000))
+    prob = cs.Problem.from_sky(sky, "fp64")
+    for sh in (1, 0):
+        prob.set_schedule(4, 0, 1, sh)
+        compare(sky, prob, "fp64")
 
 
 def test_fp32_input_dtype():
@@ -161,12 +172,20 @@ def test_batched_equals_per_item_and_schedules_bit_identical():
         f1, g1, _, _ = one.cs_likelihood_grad(torch.as_tensor(sky.x[b], device="cuda"))
         assert f1.item() == f[b]
         assert np.array_equal(g1.cpu().numpy(), g[off[b]:off[b + 1]])
-    for wpb in (1, 2, 8):
-        for bpc in (0, 2):
-            for xr in (0, 1):
-                prob.set_schedule(wpb, bpc, xr)
-                f2, g2, _, _ = gpu_eval(prob, sky, cluster=False)
-                assert np.array_equal(f2, f) and np.array_equal(g2, g)
+    # schedules move work between wavefronts only: bit-identical within one arithmetic mode;
+    # the per-pixel and segment-shared modes differ by rounding order only
+    for sh in (1, 0):
+        ref = None
+        for wpb in (1, 2, 8):
+            for bpc in (0, 2):
+                for xr in (0, 1):
+                    prob.set_schedule(wpb, bpc, xr, sh)
+                    f2, g2, _, _ = gpu_eval(prob, sky, cluster=False)
+                    if ref is None:
+                        ref = (f2, g2)
+                        assert np.all(np.abs(f2 - f) <= 1e-13 * np.abs(f))
+                        assert np.max(np.abs(g2 - g)) <= 1e-11 * np.max(np.abs(g))
+                    assert np.array_equal(f2, ref[0]) and np.array_equal(g2, ref[1])
 
 
 def test_likelihood_without_gradient_matches():

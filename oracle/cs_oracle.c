@@ -295,6 +295,61 @@ double orc_data_chi2(const orc_problem *pr) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
+/* Component maps s_hat = W d (Sec. 2.3 eq. recon_operator) and the CMB map variance           */
+/* sigma^2_CMB = Var_{p in M}[s_hat_CMB,p] summed over Q and U (Sec. 2.4 eq. min_var)           */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * s_out[2][3][P] (nullable): the GLS amplitudes (CMB, dust, synchrotron) per Stokes and pixel;
+ * NaN at excluded pixels and at pixels whose A^T N^-1 A is not positive definite.  cmb_var
+ * (nullable): population variance over the included pixels of s_hat_CMB for Q plus that for U
+ * (two-pass, Neumaier sums in ascending pixel order); NaN if a pixel is not positive definite or
+ * no pixel is included.
+ */
+int orc_component_maps(const orc_problem *pr, const double *x, double *s_out, double *cmb_var) {
+    int rc = orc_check_labels(pr);
+    if (rc) return rc;
+    const int64_t P = pr->npix;
+    int status = 0;
+    double *cmb = (double *)malloc(sizeof(double) * 2 * (size_t)(P > 0 ? P : 1));
+    int64_t n = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        double sh[6];
+        if (pr->labels[p] < 0) {
+            if (s_out)
+                for (int k = 0; k < 6; ++k) s_out[k * P + p] = NAN;
+            continue;
+        }
+        const int st = orc_pixel(pr, x, (int32_t)p, NULL, NULL, sh, NULL, NULL, NULL);
+        status |= st;
+        if (st & ORC_NOT_PD)
+            for (int k = 0; k < 6; ++k) sh[k] = NAN;
+        if (s_out)
+            for (int k = 0; k < 6; ++k) s_out[k * P + p] = sh[k];
+        cmb[2 * n] = sh[0];
+        cmb[2 * n + 1] = sh[3];
+        ++n;
+    }
+    if (cmb_var && (n == 0 || (status & ORC_NOT_PD))) {
+        *cmb_var = NAN;
+    } else if (cmb_var) {
+        double var = 0.0;
+        for (int s = 0; s < 2 && n > 0; ++s) {
+            orc_sum m = {0.0, 0.0}, v = {0.0, 0.0};
+            for (int64_t i = 0; i < n; ++i) orc_add(&m, cmb[2 * i + s]);
+            double mean = orc_val(&m) / (double)n;
+            for (int64_t i = 0; i < n; ++i) {
+                double dv = cmb[2 * i + s] - mean;
+                orc_add(&v, dv * dv);
+            }
+            var += orc_val(&v) / (double)n;
+        }
+        *cmb_var = var;
+    }
+    free(cmb);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------------ */
 /* Segments of one labelling: stable counting sort of pixel indices by cluster (Sec. 2.2)     */
 /* ------------------------------------------------------------------------------------------ */
 /*

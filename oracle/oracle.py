@@ -59,6 +59,7 @@ def lib():
         L.orc_check_labels.argtypes = [P(_Problem)]
         L.orc_pixel.argtypes = [P(_Problem), dp, C.c_int32, dp, dp, dp, dp, dp, dp]
         L.orc_likelihood_grad.argtypes = [P(_Problem), dp, dp, dp, dp]
+        L.orc_component_maps.argtypes = [P(_Problem), dp, dp, dp]
         L.orc_data_chi2.argtypes = [P(_Problem)]
         L.orc_data_chi2.restype = C.c_double
         L.orc_segments.argtypes = [C.c_int64, ip, C.c_int32, ip, ip]
@@ -129,6 +130,17 @@ class Problem:
         g = np.zeros(3)
         st = lib().orc_pixel(C.byref(self._s), _dp(x), int(p), _dp(m), _dp(b), _dp(s), _dp(r), _dp(f), _dp(g))
         return dict(M=m, b=b, s=s, r=r, f=float(f[0]), g=g, status=st)
+
+    def component_maps(self, x):
+        """GLS amplitudes ``s_hat[2][3][P]`` (NaN where excluded) and sigma^2_CMB (Q + U)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        P = self.labels.shape[1]
+        s = np.zeros((2, 3, P))
+        v = np.zeros(1)
+        st = lib().orc_component_maps(C.byref(self._s), _dp(x), _dp(s), _dp(v))
+        if st < 0:
+            raise ValueError(f"oracle error {st}")
+        return s, float(v[0]), st
 
     def data_chi2(self) -> float:
         return lib().orc_data_chi2(C.byref(self._s))

@@ -461,3 +461,56 @@ def test_lbfgs_kkt_at_result():
     assert st & O.CONVERGED
     assert np.linalg.norm(gi[free]) <= 1e-8 * np.linalg.norm(g0i[free0])
     assert np.all((x >= lo) & (x <= hi))
+
+
+def test_oracle_regression_fixture():
+    # values written by tests/golden/make_golden.py (oracle only); guards against silent changes
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_workload1.json")))
+    sky = skygen.make_config(1)
+    pr = O.Problem.from_sky(sky, 0)
+    for pt in fx["points"]:
+        f, g, _, st = pr.likelihood_grad(np.array(pt["x"]))
+        assert abs(f - pt["neg2logL"]) <= 1e-13 * abs(pt["neg2logL"])
+        assert np.allclose(g, pt["grad"], rtol=1e-11, atol=1e-11 * np.max(np.abs(pt["grad"])))
+
+
+def test_component_maps_match_lstsq_and_numpy_variance():
+    # s_hat = W d (Sec. 2.3 eq. recon_operator) against numpy lstsq on the intensity-route A;
+    # sigma^2_CMB (Sec. 2.4 eq. min_var) against numpy's population variance, Q plus U
+    sky = skygen.make_tiny(60, 15, (3, 2, 2), seed=18, mask_frac=0.2)
+    pr = O.Problem.from_sky(sky)
+    x = sky.x[0]
+    s, var, st = pr.component_maps(x)
+    lab = sky.item_labels(0)
+    d = sky.item_d(0)
+    K = sky.nclusters[0]
+    off = [0, K[0], K[0] + K[1]]
+    cmb = [[], []]
+    for p in range(sky.npix):
+        if lab[0, p] < 0:
+            assert np.all(np.isnan(s[:, :, p]))
+            continue
+        bd, td, bs = x[off[0] + lab[0, p]], x[off[1] + lab[1, p]], x[off[2] + lab[2, p]]
+        A = np.stack([np.ones(sky.nfreq), skygen.sky_sed_dust(sky.freqs, bd, td), skygen.sky_sed_sync(sky.freqs, bs)], 1)
+        for q in range(2):
+            sw = np.sqrt(sky.ninv[q])
+            sol = np.linalg.lstsq(sw[:, None] * A, sw * d[q, :, p], rcond=None)[0]
+            assert np.allclose(s[q, :, p], sol, rtol=1e-9, atol=1e-9 * np.max(np.abs(sol)))
+            cmb[q].append(sol[0])
+    ref = np.var(cmb[0]) + np.var(cmb[1])
+    assert abs(var - ref) <= 1e-10 * ref
+
+
+def test_component_maps_nan_rules():
+    # a pixel without information (zero weights) has no amplitudes; the variance is then undefined
+    sky = skygen.make_tiny(6, 15, (1, 1, 1), seed=13)
+    w = np.repeat(sky.ninv[:, :, None], 6, axis=2)
+    w[:, :, 2] = 0.0
+    s, var, st = O.Problem(sky.freqs, sky.item_d(0), w, sky.item_labels(0), (1, 1, 1)).component_maps(sky.x[0])
+    assert st & O.NOT_PD and math.isnan(var)
+    assert np.all(np.isnan(s[:, :, 2])) and np.all(np.isfinite(np.delete(s, 2, axis=2)))
+    lab = np.full((3, 6), -1, dtype=np.int32)  # nothing included
+    s, var, st = O.Problem(sky.freqs, sky.item_d(0), sky.ninv, lab, (1, 1, 1)).component_maps(sky.x[0])
+    assert st == 0 and math.isnan(var) and np.all(np.isnan(s))

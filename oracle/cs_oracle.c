@@ -11,8 +11,11 @@
  *   Sec. 2.1, eq. (mixing_columns)      CMB = 1; dust modified blackbody; synchrotron power law
  *   Sec. 2.1, eq. (mle_solution)        s_hat = (A^T N^-1 A)^-1 A^T N^-1 d
  *   Sec. 2.1, eq. (spectral_likelihood) ln L_spec = const + 1/2 sum_p b^T M^-1 b
- *   Sec. 2.2                            beta_p = beta_k for p in patch k
+ *   Sec. 2.2                            beta_p = beta_k for p in patch k; spherical K-means
+ *                                       (mean of unit vectors renormalised, angular distance)
  *   Sec. 2.3                            one independent patching per spectral parameter
+ *   Sec. 2.3, eq. (recon_operator)      component maps s_hat = W d
+ *   Sec. 2.4, eq. (min_var)             variance of the reconstructed CMB over the mask
  *   Sec. 3.3.1 (gradient equation)      gradient from the GLS residuals with s held fixed
  *   App. A.1 and Alg. 1                 affine internal box [0,1], clamp to the nearest bound
  *
@@ -582,4 +585,82 @@ int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double 
     free(buf);
     free(fr);
     return status;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Spherical K-means (Sec. 2.2): Lloyd iterations on unit vectors with angular distance        */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * vecs[n][3]: unit vectors in ascending pixel order; init[k]: distinct indices into vecs (the
+ * random draw of the initial centroids is an input).  The nearest centroid in angular separation
+ * is the one of largest dot product; the dot product is (x cx + y cy) + z cz with every product
+ * and sum rounded separately, and a tie goes to the lowest centroid index.  Each of the iters
+ * iterations assigns every vector, then replaces each centroid by the sum of its members (in
+ * ascending index order) divided by its Euclidean norm; a cluster without members (or with a
+ * zero sum) keeps its centroid.  The labels come from one more assignment and are compacted to
+ * 0..K_eff-1 in ascending centroid index.  With k >= n every vector is its own cluster (the
+ * patch-count cap).  labels[n] out; returns K_eff, or ORC_E_INVALID.
+ */
+static double orc_dot3(const double *a, const double *c) {
+    double xy = a[0] * c[0] + a[1] * c[1];
+    return xy + a[2] * c[2];
+}
+
+static void orc_km_assign(int64_t n, const double *v, int32_t k, const double *c, int32_t *lab) {
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t best = 0;
+        double bd = orc_dot3(v + 3 * i, c);
+        for (int32_t j = 1; j < k; ++j) {
+            double dj = orc_dot3(v + 3 * i, c + 3 * j);
+            if (dj > bd) {
+                bd = dj;
+                best = j;
+            }
+        }
+        lab[i] = best;
+    }
+}
+
+int32_t orc_kmeans(int64_t n, const double *vecs, int32_t k, const int32_t *init, int32_t iters,
+                   int32_t *labels) {
+    if (n < 0 || k < 1 || iters < 0) return ORC_E_INVALID;
+    if ((int64_t)k >= n) {
+        for (int64_t i = 0; i < n; ++i) labels[i] = (int32_t)i;
+        return (int32_t)n;
+    }
+    double *c = (double *)malloc(sizeof(double) * 3 * (size_t)k);
+    double *sum = (double *)malloc(sizeof(double) * 3 * (size_t)k);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int32_t *remap = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    for (int32_t j = 0; j < k; ++j) {
+        if (init[j] < 0 || init[j] >= n) {
+            free(c); free(sum); free(cnt); free(remap);
+            return ORC_E_INVALID;
+        }
+        memcpy(c + 3 * j, vecs + 3 * (int64_t)init[j], sizeof(double) * 3);
+    }
+    for (int32_t it = 0; it < iters; ++it) {
+        orc_km_assign(n, vecs, k, c, labels);
+        memset(sum, 0, sizeof(double) * 3 * (size_t)k);
+        memset(cnt, 0, sizeof(int64_t) * (size_t)k);
+        for (int64_t i = 0; i < n; ++i) {
+            double *sj = sum + 3 * labels[i];
+            for (int d = 0; d < 3; ++d) sj[d] += vecs[3 * i + d];
+            cnt[labels[i]] += 1;
+        }
+        for (int32_t j = 0; j < k; ++j) {
+            const double *sj = sum + 3 * j;
+            double nrm = sqrt((sj[0] * sj[0] + sj[1] * sj[1]) + sj[2] * sj[2]);
+            if (cnt[j] > 0 && nrm > 0.0)
+                for (int d = 0; d < 3; ++d) c[3 * j + d] = sj[d] / nrm;
+        }
+    }
+    orc_km_assign(n, vecs, k, c, labels);
+    for (int32_t j = 0; j < k; ++j) remap[j] = 0;
+    for (int64_t i = 0; i < n; ++i) remap[labels[i]] = 1;
+    int32_t keff = 0;
+    for (int32_t j = 0; j < k; ++j) remap[j] = remap[j] ? keff++ : -1;
+    for (int64_t i = 0; i < n; ++i) labels[i] = remap[labels[i]];
+    free(c); free(sum); free(cnt); free(remap);
+    return keff;
 }

@@ -64,6 +64,8 @@ def lib():
         L.orc_data_chi2.restype = C.c_double
         L.orc_segments.argtypes = [C.c_int64, ip, C.c_int32, ip, ip]
         L.orc_segments.restype = C.c_int64
+        L.orc_kmeans.argtypes = [C.c_int64, dp, C.c_int32, ip, C.c_int32, ip]
+        L.orc_kmeans.restype = C.c_int32
         L.orc_lbfgs.argtypes = [P(_Problem), dp, dp, dp, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                 C.c_double, dp, P(C.c_int32), P(C.c_int64)]
         _lib = L
@@ -180,3 +182,16 @@ def segments(labels_j, k: int):
     if n < 0:
         raise ValueError(f"oracle error {n}")
     return perm[:n].copy(), off
+
+
+def kmeans(vecs, k: int, init, iters: int = 20):
+    """Spherical K-means of unit vectors ``vecs[n][3]``; returns ``(labels[n], K_eff)``."""
+    v = np.ascontiguousarray(vecs, dtype=np.float64)
+    n = v.shape[0]
+    ini = np.ascontiguousarray(init, dtype=np.int32)
+    assert ini.size >= min(k, n) or k >= n
+    lab = np.zeros(max(n, 1), dtype=np.int32)
+    keff = lib().orc_kmeans(n, _dp(v), int(k), _ip(ini) if ini.size else None, int(iters), _ip(lab))
+    if keff < 0:
+        raise ValueError(f"oracle error {keff}")
+    return lab[:n].copy(), int(keff)

@@ -514,3 +514,90 @@ def test_component_maps_nan_rules():
     lab = np.full((3, 6), -1, dtype=np.int32)  # nothing included
     s, var, st = O.Problem(sky.freqs, sky.item_d(0), sky.ninv, lab, (1, 1, 1)).component_maps(sky.x[0])
     assert st == 0 and math.isnan(var) and np.all(np.isnan(s))
+
+
+# --------------------------------------------------------------------------------------------
+# spherical K-means (Sec. 2.2)
+# --------------------------------------------------------------------------------------------
+
+def _partition(lab):
+    return sorted(tuple(np.flatnonzero(lab == v)) for v in np.unique(lab))
+
+
+def _lloyd_score(v, lab):
+    # sum over clusters of |sum of members|: the spherical K-means objective at its best centroids
+    return sum(np.linalg.norm(v[lab == c].sum(0)) for c in np.unique(lab))
+
+
+def test_kmeans_recovers_well_separated_groups():
+    g = np.random.default_rng(3)
+    centres = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, -1.0], [-0.6, -0.8, 0]])
+    pts, truth = [], []
+    for c, ctr in enumerate(centres):
+        x = ctr + 0.05 * g.standard_normal((40, 3))
+        pts.append(x / np.linalg.norm(x, axis=1, keepdims=True))
+        truth += [c] * 40
+    v = np.concatenate(pts)
+    truth = np.array(truth)
+    init = np.array([0, 40, 80, 120], dtype=np.int32)  # one seed per group, ascending
+    lab, keff = O.kmeans(v, 4, init)
+    assert keff == 4 and np.array_equal(lab, truth)
+    # rotating the sphere rotates the clustering
+    q, _ = np.linalg.qr(g.standard_normal((3, 3)))
+    lab_r, _ = O.kmeans(v @ q.T, 4, init)
+    assert np.array_equal(lab_r, truth)
+
+
+def test_kmeans_output_is_a_lloyd_fixed_point_and_objective_rises():
+    g = np.random.default_rng(4)
+    v = skygen.sky.positions(500, g)
+    init = np.sort(g.choice(500, 12, replace=False)).astype(np.int32)
+    lab, keff = O.kmeans(v, 12, init, iters=200)
+    # fixed point, recomputed with numpy: each point's label is its nearest normalised mean
+    cen = np.stack([v[lab == c].sum(0) for c in range(keff)])
+    cen /= np.linalg.norm(cen, axis=1, keepdims=True)
+    dots = v @ cen.T
+    assert np.all(dots[np.arange(500), lab] >= dots.max(1) - 1e-12)
+    # the objective never decreases along the Lloyd iterations
+    scores = [_lloyd_score(v, O.kmeans(v, 12, init, iters=t)[0]) for t in range(0, 15)]
+    assert all(b >= a - 1e-9 for a, b in zip(scores, scores[1:]))
+
+
+def test_kmeans_ties_empty_clusters_and_cap():
+    g = np.random.default_rng(5)
+    v = skygen.sky.positions(60, g)
+    v = np.concatenate([v, v[:1]])  # point 60 duplicates point 0
+    # centroids 1 and 2 start on identical vectors: every point prefers index 1 (lowest), so with
+    # no update cluster 2 has no member and is compacted away
+    init = np.array([5, 0, 60], dtype=np.int32)
+    lab, keff = O.kmeans(v, 3, init, iters=0)
+    assert keff == 2 and set(np.unique(lab)) == {0, 1}
+    lab2, _ = O.kmeans(v, 2, init[:2], iters=0)
+    assert np.array_equal(lab, lab2)
+    # one update: cluster 2 was empty, so it keeps its starting vector while clusters 0 and 1 move
+    # to their normalised means (computed here with numpy); the final assignment uses those three
+    a0 = np.argmax(v @ v[init[:2]].T, axis=1)
+    cen = np.stack([v[a0 == c].sum(0) for c in range(2)] + [v[0]])
+    cen[:2] /= np.linalg.norm(cen[:2], axis=1, keepdims=True)
+    want = np.argmax(v @ cen.T, axis=1)
+    lab, keff = O.kmeans(v, 3, init, iters=1)
+    assert _partition(lab) == _partition(want)
+    # the cap: k >= n gives every vector its own cluster, by rank
+    lab, keff = O.kmeans(v[:7], 7, np.arange(7, dtype=np.int32))
+    assert keff == 7 and np.array_equal(lab, np.arange(7))
+    lab, keff = O.kmeans(v, 1, np.array([9], dtype=np.int32))
+    assert keff == 1 and np.all(lab == 0)
+
+
+def test_kmeans_agrees_with_independent_generator_implementation():
+    # the seeded sky generator carries its own K-means (tensor cumulative sums, a different
+    # rounding order); labels may differ only where rounding decides a near-tie
+    g = np.random.default_rng(6)
+    v = skygen.sky.positions(3072, g)
+    for k in (1, 17, 300):
+        gi = np.random.default_rng(100 + k)
+        init = gi.choice(3072, size=k, replace=False)
+        lab_gen, keff_gen = skygen.sky.spherical_kmeans(v, k, np.random.default_rng(100 + k))
+        lab, keff = O.kmeans(v, k, init.astype(np.int32))
+        assert keff == keff_gen
+        assert np.mean(lab == lab_gen) >= 0.999, k

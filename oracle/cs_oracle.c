@@ -18,6 +18,7 @@
  *   Sec. 2.4, eq. (min_var)             variance of the reconstructed CMB over the mask
  *   Sec. 3.3.1 (gradient equation)      gradient from the GLS residuals with s held fixed
  *   App. A.1 and Alg. 1                 affine internal box [0,1], clamp to the nearest bound
+ *   App. A (AdaTopK)                    AdaBelief steps, Top-K release, rescaling, step limit
  *
  * Readings where the paper is silent (each one also listed in the design notes):
  *   - objective F = -2 ln L_spec with the constant dropped: F = -sum_p sum_{Q,U} b^T M^-1 b;
@@ -584,6 +585,203 @@ int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double 
     if (nevals_out) *nevals_out = o.nevals;
     free(buf);
     free(fr);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* AdaTopK (App. A): AdaBelief directions, Top-K release of bound constraints, dynamic         */
+/* rescaling, step limit at the nearest bound, backtracking line search                         */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * Internal box y = (x - l)/(u - l) (App. A.1); gradients g = dF/dx (u - l).  Pivot p_i = -1 at the
+ * lower bound, +1 at the upper bound, 0 free; set at the start for coordinates on a bound.  Each
+ * iteration:
+ *   1. release: among pinned coordinates whose score p_i g_i is positive (the descent direction
+ *      points into the box), the n_rel = max(1, floor(topk n_cand)) largest scores are freed
+ *      (ties: lowest index);
+ *   2. projected gradient gp = g on the free set; CONVERGED when |gp|_2 <= gtol |gp_first|_2;
+ *   3. rescaling: with scale c (initially 1), if |c gp|_2 leaves [1e-15, 1e15] then
+ *      c <- c / |c gp|_2 and the moments m, v are multiplied by the factor and its square;
+ *   4. AdaBelief on c gp (step count t): m = b1 m + (1-b1) c gp; v = b2 v + (1-b2)(c gp - m)^2
+ *      + eps; direction d = -lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps) on the free set;
+ *   5. step limit a_max = min over free i with d_i != 0 of the distance to the bound along d
+ *      (limiting index: lowest on ties); a_max = 0 pins the limiting coordinate at once;
+ *   6. line search from a = min(a_max, a_0), a_0 = min(1, 2 a_prev) with a_prev the last accepted
+ *      step (1 at the start and after a reset), halving at most max_backtracks times; the trial is
+ *      y + a d clipped into the box, with the limiting coordinate set on its bound when
+ *      a = a_max.  Accepted when it moves y and either decreases F (Armijo with c1 when
+ *      g.(y_t - y) < 0, strictly otherwise) or leaves F unchanged to 1e-12 relative with
+ *      g_t.(y_t - y) <= 0.  A step accepted at a = a_max pins the limiting coordinate;
+ *   7. no acceptable trial: with t > 1 the moments are reset (m = v = 0, t = 0) and y stays;
+ *      with t = 1 the item stops with LS_FAIL.
+ * MAXITER after max_iter iterations (accepted steps, pins and resets each count one).
+ */
+int orc_adatopk(const orc_problem *pr, const double *lo, const double *hi, double *x, double lr,
+                double b1, double b2, double eps, double topk, double gtol, int32_t max_iter,
+                int32_t max_backtracks, double c1, double *fout, int32_t *iters_out,
+                int64_t *nevals_out) {
+    const int K = pr->nclusters[0] + pr->nclusters[1] + pr->nclusters[2];
+    if (K < 1 || !(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) ||
+        !(eps >= 0.0) || !(topk >= 0.0 && topk <= 1.0))
+        return ORC_E_INVALID;
+    for (int i = 0; i < K; ++i)
+        if (!(hi[i] > lo[i])) return ORC_E_INVALID;
+    double *buf = (double *)calloc((size_t)K * 10, sizeof(double));
+    double *y = buf, *g = y + K, *mm = g + K, *vv = mm + K, *d = vv + K, *yt = d + K, *gt = yt + K,
+           *xp = gt + K, *gp = xp + K, *sc = gp + K;
+    int *piv = (int *)calloc((size_t)K, sizeof(int));
+    orc_obj o = {pr, lo, hi, K, xp, gp, 0};
+    int status = 0, iters = 0, t = 0, have_pg0 = 0;
+    double f, ft, c = 1.0, pg0 = 0.0, b1t = 1.0, b2t = 1.0, aprev = 1.0;
+
+    for (int i = 0; i < K; ++i) {
+        double yi = (x[i] - lo[i]) / (hi[i] - lo[i]);
+        y[i] = yi < 0.0 ? 0.0 : (yi > 1.0 ? 1.0 : yi);
+        piv[i] = y[i] <= 0.0 ? -1 : (y[i] >= 1.0 ? 1 : 0);
+    }
+    int st = orc_eval_internal(&o, y, &f, g);
+    if (st < 0) {
+        free(buf);
+        free(piv);
+        return st;
+    }
+    status |= st & (ORC_NOT_PD | ORC_NONFINITE);
+    if (!isfinite(f)) status |= ORC_NONFINITE;
+
+    while (!(status & (ORC_CONVERGED | ORC_NONFINITE | ORC_NOT_PD | ORC_LS_FAIL))) {
+        /* 1. Top-K release */
+        int ncand = 0;
+        for (int i = 0; i < K; ++i) {
+            sc[i] = piv[i] ? piv[i] * g[i] : 0.0;
+            if (piv[i] && sc[i] > 0.0) ++ncand;
+        }
+        if (ncand > 0) {
+            int nrel = (int)floor(topk * ncand);
+            if (nrel < 1) nrel = 1;
+            for (int r = 0; r < nrel; ++r) {
+                int best = -1;
+                for (int i = 0; i < K; ++i)
+                    if (piv[i] && sc[i] > 0.0 && (best < 0 || sc[i] > sc[best])) best = i;
+                if (best < 0) break;
+                piv[best] = 0;
+            }
+        }
+        /* 2. projected gradient and the stopping test */
+        double pg = 0.0;
+        for (int i = 0; i < K; ++i)
+            if (!piv[i]) pg += g[i] * g[i];
+        pg = sqrt(pg);
+        if (!have_pg0) {
+            pg0 = pg;
+            have_pg0 = 1;
+        }
+        if (pg <= gtol * pg0) {
+            status |= ORC_CONVERGED;
+            break;
+        }
+        if (iters >= max_iter) {
+            status |= ORC_MAXITER;
+            break;
+        }
+        /* 3. dynamic rescaling of the objective and of the moments */
+        double cpg = c * pg;
+        if (cpg < 1e-15 || cpg > 1e15) {
+            double fs = 1.0 / cpg;
+            c *= fs;
+            for (int i = 0; i < K; ++i) {
+                mm[i] *= fs;
+                vv[i] *= fs * fs;
+            }
+        }
+        /* 4. AdaBelief direction */
+        ++t;
+        b1t *= b1;
+        b2t *= b2;
+        for (int i = 0; i < K; ++i) {
+            double gi = piv[i] ? 0.0 : c * g[i];
+            mm[i] = b1 * mm[i] + (1.0 - b1) * gi;
+            double dv = gi - mm[i];
+            vv[i] = b2 * vv[i] + (1.0 - b2) * dv * dv + eps;
+            double mh = mm[i] / (1.0 - b1t), vh = vv[i] / (1.0 - b2t);
+            d[i] = piv[i] ? 0.0 : -lr * mh / (sqrt(vh) + eps);
+        }
+        /* 5. distance to the nearest bound along d */
+        double amax = INFINITY;
+        int lim = -1;
+        for (int i = 0; i < K; ++i) {
+            if (piv[i] || d[i] == 0.0) continue;
+            double a = d[i] > 0.0 ? (1.0 - y[i]) / d[i] : -y[i] / d[i];
+            if (a < amax) {
+                amax = a;
+                lim = i;
+            }
+        }
+        if (lim >= 0 && amax <= 0.0) {
+            piv[lim] = d[lim] > 0.0 ? 1 : -1;
+            y[lim] = d[lim] > 0.0 ? 1.0 : 0.0;
+            ++iters;
+            continue;
+        }
+        /* 6. backtracking line search */
+        const double a0 = 2.0 * aprev < 1.0 ? 2.0 * aprev : 1.0;
+        double alpha = amax < a0 ? amax : a0;
+        int accepted = 0, at_bound = 0;
+        for (int bt = 0; bt <= max_backtracks; ++bt) {
+            const int hit = (lim >= 0 && alpha == amax);
+            double dec = 0.0, moved = 0.0;
+            for (int i = 0; i < K; ++i) {
+                double v = y[i] + alpha * d[i];
+                yt[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+            }
+            if (hit) yt[lim] = d[lim] > 0.0 ? 1.0 : 0.0;
+            for (int i = 0; i < K; ++i) {
+                dec += g[i] * (yt[i] - y[i]);
+                moved += (yt[i] - y[i]) * (yt[i] - y[i]);
+            }
+            st = orc_eval_internal(&o, yt, &ft, gt);
+            if (st < 0) {
+                free(buf);
+                free(piv);
+                return st;
+            }
+            if (!(st & ORC_NOT_PD) && isfinite(ft) && moved > 0.0) {
+                double gd = 0.0;
+                for (int i = 0; i < K; ++i) gd += gt[i] * (yt[i] - y[i]);
+                int ok = dec < 0.0 ? (ft <= f + c1 * dec) : (ft < f);
+                if (ok || (fabs(ft - f) <= ORC_FLAT_REL * fabs(f) && gd <= 0.0)) {
+                    accepted = 1;
+                    at_bound = hit;
+                    break;
+                }
+            }
+            alpha *= 0.5;
+        }
+        if (!accepted) {
+            if (t <= 1) {
+                status |= ORC_LS_FAIL;
+                break;
+            }
+            memset(mm, 0, sizeof(double) * K);
+            memset(vv, 0, sizeof(double) * K);
+            t = 0;
+            b1t = b2t = 1.0;
+            aprev = 1.0;
+            ++iters;
+            continue;
+        }
+        aprev = alpha;
+        if (at_bound) piv[lim] = d[lim] > 0.0 ? 1 : -1;
+        memcpy(y, yt, sizeof(double) * K);
+        memcpy(g, gt, sizeof(double) * K);
+        f = ft;
+        ++iters;
+    }
+    for (int i = 0; i < K; ++i) x[i] = lo[i] + y[i] * (hi[i] - lo[i]);
+    if (fout) *fout = f;
+    if (iters_out) *iters_out = iters;
+    if (nevals_out) *nevals_out = o.nevals;
+    free(buf);
+    free(piv);
     return status;
 }
 

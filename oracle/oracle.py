@@ -64,6 +64,8 @@ def lib():
         L.orc_data_chi2.restype = C.c_double
         L.orc_segments.argtypes = [C.c_int64, ip, C.c_int32, ip, ip]
         L.orc_segments.restype = C.c_int64
+        L.orc_adatopk.argtypes = [P(_Problem), dp, dp, dp] + [C.c_double] * 6 + [C.c_int32, C.c_int32, C.c_double,
+                                                                                 dp, P(C.c_int32), P(C.c_int64)]
         L.orc_kmeans.argtypes = [C.c_int64, dp, C.c_int32, ip, C.c_int32, ip]
         L.orc_kmeans.restype = C.c_int32
         L.orc_lbfgs.argtypes = [P(_Problem), dp, dp, dp, C.c_int32, C.c_double, C.c_int32, C.c_int32,
@@ -157,6 +159,21 @@ class Problem:
         ne = C.c_int64(0)
         st = lib().orc_lbfgs(C.byref(self._s), _dp(lo), _dp(hi), _dp(x), m, gtol, max_iter, max_backtracks, c1,
                              _dp(f), C.byref(it), C.byref(ne))
+        if st < 0:
+            raise ValueError(f"oracle error {st}")
+        return x, float(f[0]), it.value, ne.value, st
+
+    def adatopk(self, x0, lo, hi, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-16, topk=0.0, gtol=1e-8, max_iter=1000,
+                 max_backtracks=30, c1=1e-4):
+        """AdaTopK (App. A); returns ``(x, F, iters, nevals, status)``."""
+        x = np.array(x0, dtype=np.float64, copy=True)
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        f = np.zeros(1)
+        it = C.c_int32(0)
+        ne = C.c_int64(0)
+        st = lib().orc_adatopk(C.byref(self._s), _dp(lo), _dp(hi), _dp(x), lr, beta1, beta2, eps, topk, gtol, max_iter,
+                               max_backtracks, c1, _dp(f), C.byref(it), C.byref(ne))
         if st < 0:
             raise ValueError(f"oracle error {st}")
         return x, float(f[0]), it.value, ne.value, st

@@ -601,3 +601,66 @@ def test_kmeans_agrees_with_independent_generator_implementation():
         lab, keff = O.kmeans(v, k, init.astype(np.int32))
         assert keff == keff_gen
         assert np.mean(lab == lab_gen) >= 0.999, k
+
+
+# --------------------------------------------------------------------------------------------
+# AdaTopK (App. A)
+# --------------------------------------------------------------------------------------------
+
+def _scipy_opt(pr, x0, lo, hi):
+    return scipy.optimize.minimize(lambda z: pr.likelihood_grad(z)[0], x0, jac=lambda z: pr.likelihood_grad(z)[1],
+                                   method="L-BFGS-B", bounds=list(zip(lo, hi)),
+                                   options=dict(ftol=1e-16, gtol=1e-12, maxiter=5000))
+
+
+def test_adatopk_matches_scipy_optimum():
+    sky = skygen.make_tiny(16, 15, (2, 1, 1), seed=16, model_consistent=True)
+    pr = O.Problem.from_sky(sky)
+    lo, hi = sky.lower[0], sky.upper[0]
+    x0 = np.array([1.54, 1.54, 20.0, -3.0])
+    x, f, it, ne, st = pr.adatopk(x0, lo, hi, max_iter=3000)
+    assert st & O.CONVERGED, st
+    res = _scipy_opt(pr, x0, lo, hi)
+    assert f <= res.fun + 1e-12 * abs(res.fun)
+    assert np.all(np.abs(x - res.x) <= 1e-4 * np.maximum(1.0, np.abs(res.x)))
+
+
+def test_adatopk_pins_an_active_bound_and_meets_kkt():
+    # the truth puts beta_d above the box: the optimum sits on the upper bound
+    sky = skygen.make_tiny(16, 15, (1, 1, 1), seed=19, model_consistent=True, noiseless=True)
+    pr = O.Problem.from_sky(sky)
+    lo, hi = sky.lower[0].copy(), sky.upper[0].copy()
+    hi[0] = sky.x[0][0] - 0.2  # beta_d bound below its true value
+    x, f, it, ne, st = pr.adatopk(np.array(skygen.X0), lo, hi, max_iter=3000)
+    assert st & O.CONVERGED, st
+    assert x[0] == hi[0]  # pinned exactly on the bound
+    _, g, _, _ = pr.likelihood_grad(x)
+    assert g[0] < 0  # F still decreases outward: the bound is active
+    res = _scipy_opt(pr, np.array(skygen.X0), lo, hi)
+    assert np.all(np.abs(x - res.x) <= 1e-4 * np.maximum(1.0, np.abs(res.x)))
+
+
+def test_adatopk_rescaling_makes_tiny_objectives_behave_like_unit_ones():
+    # multiplying d by 1e-12 multiplies F and g by 1e-24; without the rescaling the AdaBelief
+    # epsilon (1e-16 inside the second moment) would dominate and the steps would vanish
+    sky = skygen.make_tiny(16, 15, (2, 1, 1), seed=16, model_consistent=True)
+    lo, hi = sky.lower[0], sky.upper[0]
+    x0 = np.array([1.54, 1.54, 20.0, -3.0])
+    pr = O.Problem.from_sky(sky)
+    pr_s = O.Problem.from_sky(sky, d=sky.item_d(0) * 1e-12)
+    x, f, it, _, st = pr.adatopk(x0, lo, hi, max_iter=3000)
+    xs, fs, its, _, sts = pr_s.adatopk(x0, lo, hi, max_iter=3000)
+    assert st & O.CONVERGED and sts & O.CONVERGED
+    assert np.all(np.abs(xs - x) <= 1e-5 * np.maximum(1.0, np.abs(x)))
+
+
+def test_adatopk_release_fraction_reaches_the_same_optimum():
+    sky = skygen.make_tiny(32, 15, (3, 2, 2), seed=17)
+    pr = O.Problem.from_sky(sky)
+    lo, hi = sky.lower[0], sky.upper[0]
+    x0 = lo.copy()  # every parameter starts pinned at its lower bound
+    x_ref = pr.lbfgs(np.concatenate([np.full(3, 1.54), np.full(2, 20.0), np.full(2, -3.0)]), lo, hi)[0]
+    for topk in (0.0, 1.0):
+        x, f, it, ne, st = pr.adatopk(x0, lo, hi, topk=topk, max_iter=5000)
+        assert st & O.CONVERGED, (topk, st)
+        assert np.all(np.abs(x - x_ref) <= 1e-4 * np.maximum(1.0, np.abs(x_ref))), topk

@@ -137,6 +137,54 @@ cs_status cs_likelihood(cs_problem *prob, const double *x, double *neg2logL, int
 cs_status cs_likelihood_grad(cs_problem *prob, const double *x, double *neg2logL, double *grad,
                              double *cluster_neg2logL, int32_t *status, void *stream);
 
+/* Component maps and the CMB map variance at x (packed, FP64).  The generalised least-squares
+ * amplitudes s_hat = (A^T N^-1 A)^-1 A^T N^-1 d of every included pixel (paper Sec. 2.3, the
+ * reconstruction operator W applied to d) are formed in FP64 from the data as stored by
+ * prepare (FP32 for the FP32 precisions).
+ *   maps      nullable device double; item b's block starts at maps + b * maps_item_stride
+ *             and is [2 Stokes Q, U][3 components CMB, dust, sync][P] in the caller's pixel
+ *             order; excluded pixels and pixels whose A^T N^-1 A is not positive definite
+ *             hold NaN.
+ *   maps_item_stride  0 = 6 P, else >= 6 P elements.
+ *   cmb_var   nullable device double [B]: population variance over the included pixels of
+ *             the CMB amplitude of Q plus that of U (Sec. 2.4, eq. min_var, the statistic that
+ *             selects the number of clusters); NaN for an item with a non-positive-definite
+ *             pixel or with no included pixel.
+ *   status    nullable device int32 [B]: item bits of this call.
+ * Asynchronous on the stream; no allocation.  Shares the workspace scratch with the
+ * evaluations, so calls on one problem must not overlap. */
+cs_status cs_component_maps(cs_problem *prob, const double *x, double *maps, int64_t maps_item_stride,
+                            double *cmb_var, int32_t *status, void *stream);
+
+/* Spherical K-means patching (paper Sec. 2.2) of ntasks independent tasks over one set of n
+ * unit vectors, on the device.  Task t clusters the vectors it keeps into k[t] patches: the
+ * nearest centroid in angular separation is the one of largest dot product (ties: lowest
+ * index), and each of the iters Lloyd iterations replaces a centroid by the direction of the
+ * sum of its members (a cluster without members keeps its centroid).  Labels come from one more
+ * assignment and are compacted to 0..K_eff-1 in ascending centroid index; with k[t] >= the kept
+ * count every kept vector is its own patch (by rank), and k[t] = 1 puts all in patch 0.  Every
+ * floating-point decision is taken in FP64 with a fixed operation order, so results are
+ * reproducible bit for bit.
+ *   vecs      device double [n][3] unit vectors (pixel order)
+ *   keep      nullable device uint8, row t at keep + t * keep_stride (0 = n): 1 = vector i takes
+ *             part in task t; null = every vector in every task
+ *   k         host int32 [ntasks], >= 1
+ *   init      device int32, row t at init + t * init_stride (0 = max k): when k[t] is below the
+ *             kept count, indices (into the task's kept vectors in ascending pixel order) of the
+ *             k[t] starting centroids -- the random draw, made by the caller
+ *   labels    device int32, row t at labels + t * labels_stride (0 = n): the patch of each
+ *             vector, -1 where not kept
+ *   keff      device int32 [ntasks]: number of patches; -1 if an init index was out of range
+ *             (that task's labels are then all -1)
+ *   workspace device, 256-byte aligned, >= cs_kmeans_workspace_bytes; caller owned.
+ * Synchronises the stream once (upload of k); the rest is asynchronous. */
+cs_status cs_kmeans_workspace_bytes(int64_t n, int32_t ntasks, const int32_t *k, size_t *bytes);
+cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep,
+                          int64_t keep_stride, const int32_t *k, const int32_t *init,
+                          int64_t init_stride, int32_t iters, int32_t *labels,
+                          int64_t labels_stride, int32_t *keff, void *workspace, size_t bytes,
+                          void *stream);
+
 /* Batched projected L-BFGS on the device (internal box y = (x - l)/(u - l), paper App. A.1;
  * bound clamping as in Alg. 1).  Defaults: m = 10, gtol_rel = 1e-8, max_iter = 1000,
  * iters_per_graph = 8, max_backtracks = 30, c1 = 1e-4, fp64_polish = 1. */

@@ -13,6 +13,7 @@ from ._lib import (  # noqa: F401
     CsError,
     Problem,
     default_opts,
+    kmeans_batch,
     load,
 )
 from .autograd import CsLikelihood, neg2logl  # noqa: F401

@@ -57,7 +57,8 @@ _lib = None
 
 EXPORTS = [
     "cs_problem_create", "cs_problem_param_offsets", "cs_problem_workspace_bytes", "cs_problem_prepare",
-    "cs_problem_item_info", "cs_problem_segments", "cs_likelihood", "cs_likelihood_grad", "cs_optim_default_opts",
+    "cs_problem_item_info", "cs_problem_segments", "cs_likelihood", "cs_likelihood_grad", "cs_component_maps",
+    "cs_kmeans_workspace_bytes", "cs_kmeans_batch", "cs_optim_default_opts",
     "cs_optimizer_workspace_bytes", "cs_optimize_batch", "cs_problem_get_schedule", "cs_problem_set_schedule",
     "cs_problem_autotune", "cs_problem_set_timing", "cs_problem_kernel_time", "cs_problem_destroy", "cs_status_str",
     "cs_last_error",
@@ -82,6 +83,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.cs_problem_segments.argtypes = [vp, i32, i32, vp, vp, vp]
     L.cs_likelihood.argtypes = [vp, vp, vp, vp, vp]
     L.cs_likelihood_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.cs_component_maps.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.cs_kmeans_workspace_bytes.argtypes = [i64, i32, P(i32), P(C.c_size_t)]
+    L.cs_kmeans_batch.argtypes = [vp, i64, i32, vp, i64, P(i32), vp, i64, i32, vp, i64, vp, vp, C.c_size_t, vp]
     L.cs_optim_default_opts.argtypes = [P(OptimOpts)]
     L.cs_optimizer_workspace_bytes.argtypes = [vp, i32, P(C.c_size_t)]
     L.cs_optimize_batch.argtypes = [vp, P(OptimOpts), vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
@@ -130,6 +134,41 @@ def default_opts(**kw) -> OptimOpts:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def kmeans_batch(vecs: torch.Tensor, k, init: torch.Tensor, keep: torch.Tensor | None = None, iters: int = 20,
+                 stream=None):
+    """Spherical K-means patching of T tasks over the unit vectors ``vecs[n][3]`` (device FP64).
+
+    ``k``: T cluster counts; ``init[T][>= max k]`` (device int32): per task, indices into the task's
+    kept vectors (ascending pixel order) of the starting centroids; ``keep[T][n]`` (device uint8,
+    optional): which vectors a task clusters.  Returns ``(labels[T][n] int32, keff[T] int32)``;
+    ``keff[t] = -1`` flags a task whose ``init`` row is out of range.
+    """
+    L = load()
+    vecs = vecs.to(torch.float64).contiguous()
+    n = vecs.shape[0]
+    kk = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(-1))
+    T = kk.size
+    init = init.to(torch.int32).contiguous()
+    if init.dim() != 2 or init.shape[0] != T:
+        raise ValueError("init must be [T][>= max k]")
+    if keep is not None:
+        keep = keep.to(torch.uint8).contiguous()
+        if keep.shape != (T, n):
+            raise ValueError("keep must be [T][n]")
+    kp = kk.ctypes.data_as(C.POINTER(C.c_int32))
+    nb = C.c_size_t()
+    _check(L.cs_kmeans_workspace_bytes(n, T, kp, C.byref(nb)), "cs_kmeans_workspace_bytes")
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=vecs.device)
+    wp = C.c_void_p((ws.data_ptr() + 255) & ~255)
+    labels = torch.empty((T, n), dtype=torch.int32, device=vecs.device)
+    keff = torch.empty(T, dtype=torch.int32, device=vecs.device)
+    _check(L.cs_kmeans_batch(_ptr(vecs), n, T, _ptr(keep), 0, kp, _ptr(init), init.shape[1], iters, _ptr(labels), 0,
+                             _ptr(keff), wp, nb.value, _stream(stream)), "cs_kmeans_batch")
+    if stream is not None:
+        ws.record_stream(stream)  # the workspace is released in that stream's order
+    return labels, keff
 
 
 class Problem:
@@ -265,6 +304,17 @@ class Problem:
         _check(load().cs_likelihood_grad(self._h, _ptr(x), _ptr(f), _ptr(g), _ptr(cf), _ptr(st), _stream(self._stream)),
                "cs_likelihood_grad")
         return f, g, cf, st
+
+    def cs_component_maps(self, x, maps: bool = True):
+        """Returns ``(maps [B][2][3][P] or None, cmb_var [B], status [B])`` (device tensors)."""
+        x = self._x(x)
+        B = self.nitems
+        m = torch.empty((B, 2, 3, self.npix), dtype=torch.float64, device=self.device) if maps else None
+        v = torch.empty(B, dtype=torch.float64, device=self.device)
+        st = torch.empty(B, dtype=torch.int32, device=self.device)
+        _check(load().cs_component_maps(self._h, _ptr(x), _ptr(m), 0, _ptr(v), _ptr(st), _stream(self._stream)),
+               "cs_component_maps")
+        return m, v, st
 
     def cs_optimize_batch(self, lower, upper, x0, opts: OptimOpts | None = None):
         L = load()

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcs.so")
-SOURCES = ["cs_api.hip", "cs_prep.hip", "cs_eval.hip", "cs_optim.hip"]
+SOURCES = ["cs_api.hip", "cs_prep.hip", "cs_eval.hip", "cs_maps.hip", "cs_kmeans.hip", "cs_optim.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

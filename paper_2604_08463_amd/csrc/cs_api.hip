@@ -1,6 +1,7 @@
 // extern "C" entry points: descriptor validation, workspace layout, segment preparation,
 // evaluation, optimiser, schedules, autotuning and kernel timing.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -351,6 +352,61 @@ cs_status cs_likelihood(cs_problem *p, const double *x, double *neg2logl, int32_
 cs_status cs_likelihood_grad(cs_problem *p, const double *x, double *neg2logl, double *grad, double *cluster_f,
                              int32_t *status, void *stream) {
     return eval_common(p, x, neg2logl, grad, cluster_f, status, true, stream);
+}
+
+cs_status cs_component_maps(cs_problem *p, const double *x, double *maps, int64_t maps_item_stride,
+                            double *cmb_var, int32_t *status, void *stream) {
+    if (!p || !x) return invalid("null argument");
+    if (maps_item_stride != 0 && maps_item_stride < 6 * (int64_t)p->P) return invalid("maps_item_stride must be 0 or >= 6 P");
+    if (!p->prepared) {
+        set_error("cs_problem_prepare has not completed");
+        return CS_E_STATE;
+    }
+    return launch_maps(p, x, maps, maps_item_stride ? maps_item_stride : 6 * (int64_t)p->P, cmb_var, status,
+                       (hipStream_t)stream);
+}
+
+static cs_status kmeans_check(int64_t n, int32_t ntasks, const int32_t *k, int64_t *ktot) {
+    if (n < 1 || n > INT32_MAX / 2 || ntasks < 1 || ntasks > 65535 || !k)
+        return invalid("K-means needs 1 <= n <= 2^30, 1 <= ntasks <= 65535 and host k");
+    int64_t t = 0;
+    for (int32_t i = 0; i < ntasks; ++i) {
+        if (k[i] < 1) return invalid("K-means cluster counts must be >= 1");
+        t += k[i];
+    }
+    *ktot = t;
+    return CS_OK;
+}
+
+cs_status cs_kmeans_workspace_bytes(int64_t n, int32_t ntasks, const int32_t *k, size_t *bytes) {
+    int64_t ktot = 0;
+    if (!bytes) return invalid("null argument");
+    const cs_status st = kmeans_check(n, ntasks, k, &ktot);
+    if (st != CS_OK) return st;
+    *bytes = kmeans_bytes(n, ntasks, ktot);
+    return CS_OK;
+}
+
+cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep, int64_t keep_stride,
+                          const int32_t *k, const int32_t *init, int64_t init_stride, int32_t iters, int32_t *labels,
+                          int64_t labels_stride, int32_t *keff, void *workspace, size_t bytes, void *stream) {
+    int64_t ktot = 0;
+    cs_status st = kmeans_check(n, ntasks, k, &ktot);
+    if (st != CS_OK) return st;
+    if (!vecs || !init || !labels || !keff) return invalid("null argument");
+    if (iters < 0) return invalid("iters must be >= 0");
+    int32_t kmax = 1;
+    for (int32_t i = 0; i < ntasks; ++i) kmax = std::max(kmax, k[i]);
+    if (keep_stride == 0) keep_stride = n;
+    if (labels_stride == 0) labels_stride = n;
+    if (init_stride == 0) init_stride = kmax;
+    if (keep_stride < n || labels_stride < n || init_stride < kmax) return invalid("row strides too small");
+    if (!workspace || ((uintptr_t)workspace & 255) || bytes < kmeans_bytes(n, ntasks, ktot)) {
+        set_error("workspace must be non-null, 256-byte aligned and at least cs_kmeans_workspace_bytes");
+        return CS_E_WORKSPACE;
+    }
+    return kmeans_batch(vecs, n, ntasks, keep, keep_stride, k, init, init_stride, iters, labels, labels_stride, keff,
+                        workspace, (hipStream_t)stream);
 }
 
 cs_status cs_optim_default_opts(cs_optim_opts *o) {

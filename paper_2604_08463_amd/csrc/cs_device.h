@@ -1,0 +1,63 @@
+// Device helpers shared by the library's kernels.
+#pragma once
+
+#include "cs_internal.h"
+
+namespace csi {
+
+// Address-space views.  Read-only data indexed uniformly across a wavefront (work units, item
+// and layout descriptors, band constants, chunk heads) is read through the constant address
+// space so that it lands in scalar registers via the scalar cache; data indexed per lane goes
+// through explicit global pointers instead of generic (flat) ones.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+    return (cptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
+
+__device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t g) {
+    int lo = 0, hi = nitems;  // largest lo with off[lo] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t lanemask_le(int lane) {
+    return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+}
+
+// Neumaier-compensated accumulation: s + c carries the sum.
+__device__ __forceinline__ void neu_add(double &s, double &c, double v) {
+    const double t = s + v;
+    if (fabs(s) >= fabs(v))
+        c += (s - t) + v;
+    else
+        c += (v - t) + s;
+    s = t;
+}
+
+// Logical block index; with xcd_remap the blocks dealt round-robin to the 8 XCDs are renumbered so
+// that each XCD works on one contiguous range of units (its own L2 sees neighbouring tables).
+__device__ __forceinline__ int64_t logical_block(int xcd_remap) {
+    const int64_t nb = gridDim.x;
+    int64_t lb = blockIdx.x;
+    if (xcd_remap) {
+        const int64_t x = lb % kNumXcd, i = lb / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
+        lb = x * q + (x < r ? x : r) + i;
+    }
+    return lb;
+}
+
+}  // namespace csi

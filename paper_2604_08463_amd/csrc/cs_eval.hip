@@ -14,7 +14,7 @@
 //   h_sk = sum_nu w d_s delta_k,   G_jk = sum_nu w a_j delta_k,
 // so dF/dtheta_k = -2 sum_s s_hat_s,col(k) (h_sk - sum_j s_hat_sj G_jk).  Both sums are
 // accumulated in the same single pass over frequency as M and b.
-#include "cs_internal.h"
+#include "cs_device.h"
 
 #ifndef CS_WAVES_PER_EU
 #define CS_WAVES_PER_EU 1
@@ -24,23 +24,6 @@
 #endif
 
 namespace csi {
-
-// Address-space views.  Read-only data indexed uniformly across a wavefront (work units, item
-// and layout descriptors, band constants, chunk heads) is read through the constant address
-// space so that it lands in scalar registers via the scalar cache; data indexed per lane goes
-// through explicit global pointers instead of generic (flat) ones.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-template <typename T>
-using gptr = const __attribute__((address_space(1))) T *;
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const T *p) {
-    return (cptr<T>)p;
-}
-template <typename T>
-__device__ __forceinline__ gptr<T> as_global(const T *p) {
-    return (gptr<T>)p;
-}
 
 // ---------------------------------------------------------------------------------------------
 // band constants in the accumulation type
@@ -62,18 +45,6 @@ struct Band<float> {
     static __device__ __forceinline__ float wsum(cptr<BandDev> b, int s) { return b->wsum[s]; }
 };
 
-__device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t g) {
-    int lo = 0, hi = nitems;  // largest lo with off[lo] <= g
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= g)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------------------------------------
 // a2: SED tables.  Rows of an item: PD[K_d][F] = (nu/nu0d)^beta_d;
 // BTDT[K_T][F][2] = ((nu/nu0d) expm1(x0)/expm1(x) g(nu)/g(nu0d),  d ln(.)/dT);
@@ -81,35 +52,32 @@ __device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t
 // ---------------------------------------------------------------------------------------------
 template <typename TT>
 __global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int64_t ktot) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ktot) return;
+    const int F = a.nfreq;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (parameter, band)
+    if (t >= ktot * F) return;
+    const int64_t g = t / F;
+    const int f = (int)(t - g * F);
     const int item = find_item(xoff, a.nitems, g);
     if (a.active && !a.active[item]) return;
     const int64_t r = g - xoff[item];
-    if (r == 0) a.istatus[item] = 0;
-    const ItemDev it = a.items[item];
-    const BandDev &B = *a.band;
-    const int F = a.nfreq;
+    if (r == 0 && f == 0) a.istatus[item] = 0;
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<BandDev> B = as_const(a.band);
     const double x = a.x[g];
-    TT *tab = (TT *)a.tables + it.tab_off * (int64_t)F;
-    if (r < it.k[0]) {
-        TT *o = tab + r * F;
-        for (int f = 0; f < F; ++f) o[f] = (TT)exp(x * B.ld[f]);
-    } else if (r < it.k[0] + it.k[1]) {
-        const int64_t kk = r - it.k[0];
-        TT *o = tab + (it.k[0] + 2 * kk) * F;
-        const double x0 = B.hk0d / x;
-        const double e0 = expm1(x0);
-        const double q0 = x0 / (-expm1(-x0));
-        for (int f = 0; f < F; ++f) {
-            const double xf = B.hk[f] / x;
-            o[2 * f] = (TT)(B.rd[f] * e0 / expm1(xf));
-            o[2 * f + 1] = (TT)((xf / (-expm1(-xf)) - q0) / x);
-        }
+    TT *tab = (TT *)a.tables + it->tab_off * (int64_t)F;
+    const int64_t k0 = it->k[0], k1 = it->k[1];
+    if (r < k0) {
+        tab[r * F + f] = (TT)exp(x * B->ld[f]);
+    } else if (r < k0 + k1) {
+        const int64_t kk = r - k0;
+        TT *o = tab + (k0 + 2 * kk) * F;
+        const double x0 = B->hk0d / x;
+        const double xf = B->hk[f] / x;
+        o[2 * f] = (TT)(B->rd[f] * expm1(x0) / expm1(xf));
+        o[2 * f + 1] = (TT)((xf / (-expm1(-xf)) - x0 / (-expm1(-x0))) / x);
     } else {
-        const int64_t kk = r - it.k[0] - it.k[1];
-        TT *o = tab + (it.k[0] + 2 * (int64_t)it.k[1] + kk) * F;
-        for (int f = 0; f < F; ++f) o[f] = (TT)(exp(x * B.ls[f]) * B.gs[f]);
+        const int64_t kk = r - k0 - k1;
+        tab[(k0 + 2 * k1 + kk) * F + f] = (TT)(exp(x * B->ls[f]) * B->gs[f]);
     }
 }
 
@@ -125,10 +93,6 @@ template <typename TA>
 struct SAcc {  // accumulators of one Stokes parameter: b and h
     TA b0, b1, b2, h1, h2, h3;
 };
-
-__device__ __forceinline__ uint64_t lanemask_le(int lane) {
-    return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-}
 
 // Band loop of one pixel: calls band(f, d_Q, d_U, PD, BT, DT, SS) for f = 0..F-1.
 // FM > 0 (compile-time band count): the pixel's whole Q/U data column is requested first (one
@@ -251,16 +215,6 @@ __device__ __forceinline__ void seg_reduce_write(uint64_t head, int lane, double
 }
 
 // WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
-__device__ __forceinline__ int64_t logical_block(int xcd_remap) {
-    const int64_t nb = gridDim.x;
-    int64_t lb = blockIdx.x;
-    if (xcd_remap) {  // blocks are dealt round-robin to the XCDs: give each XCD a contiguous range
-        const int64_t x = lb % kNumXcd, i = lb / kNumXcd, q = nb / kNumXcd, r = nb % kNumXcd;
-        lb = x * q + (x < r ? x : r) + i;
-    }
-    return lb;
-}
-
 // One 64-pixel work unit, every per-pixel sum formed by its own lane.
 template <typename TS, typename TA, bool GRAD, int WM, int FM>
 __device__ __forceinline__ void unit_pixel(const EvalArgs &a, const int item, const int chunk, const int lane) {
@@ -636,17 +590,255 @@ __global__ __launch_bounds__(512) void k_pixel_seg(const EvalArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// a7 (second level): deterministic compensated sums over each cluster's segments
+// LDS-staged pixel kernel (band weights shared by Q and U).  Each wavefront first stages, for
+// every segment of its chunk, the mixing-matrix columns (a_d, da_d/dT / a_d, a_s) of every band
+// into its own LDS slice -- one parallel round of SED-table gathers -- and, in the segment-shared
+// mode, the segments' records.  The band loop then issues only the streaming data loads (a ring
+// of kRing groups prefetched ahead) and reads the columns from LDS, whose counter is separate
+// from the vector-memory counter: no table gather ever waits behind a data load.  Chunks with
+// more than kStageSeg segments use the direct-gather path.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void neu_add(double &s, double &c, double v) {
-    const double t = s + v;
-    if (fabs(s) >= fabs(v))
-        c += (s - t) + v;
-    else
-        c += (v - t) + s;
-    s = t;
+template <typename TA>
+struct StageCfg;
+template <>
+struct StageCfg<float> {
+    static constexpr int kSeg = 16;
+};
+template <>
+struct StageCfg<double> {
+    static constexpr int kSeg = 10;
+};
+
+template <typename TA>
+struct alignas(4 * sizeof(TA)) Col4 {
+    TA ad, dt, as, pad;
+};
+
+template <typename TA>
+__host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
+    return (size_t)StageCfg<TA>::kSeg * (size_t)F * sizeof(Col4<TA>) + (size_t)StageCfg<TA>::kSeg * sizeof(SegRec);
 }
 
+template <typename TS, typename TA, bool GRAD, bool SHARED>
+__device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, const int chunk, const int lane,
+                                            char *wave_lds) {
+    constexpr int kRing = 4;  // groups of kG bands in flight per lane
+    constexpr int kG = 2;
+    const cptr<BandDev> B = as_const(a.band);
+    const int F = a.nfreq;
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
+    const uint64_t head = as_const(L->head)[chunk];
+    const int segbase = as_const(L->seg_base)[chunk];
+    const int nseg = as_const(L->seg_base)[chunk + 1] - segbase;
+    const int nvalid = L->n_incl - chunk * kChunk;
+    const bool valid = lane < nvalid;
+    const int segl = __popcll(head & lanemask_le(lane)) - 1;
+    const int64_t kd = it->k[0], kt = it->k[1];
+    const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+    const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
+    const gptr<TS> du = dq + (int64_t)F * kChunk;
+
+    // data ring: groups 0 .. kRing-1 requested before anything else
+    TS rq[kRing][kG], ru[kRing][kG];
+#pragma unroll
+    for (int r = 0; r < kRing; ++r)
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            const int f0 = r * kG + j;
+            const int f = f0 < F ? f0 : F - 1;
+            rq[r][j] = dq[f * kChunk];
+            ru[r][j] = du[f * kChunk];
+        }
+
+    // stage the columns of the chunk's segments (and their records)
+    Col4<TA> *cols = (Col4<TA> *)wave_lds;
+    SegRec *recs = (SegRec *)(wave_lds + (size_t)StageCfg<TA>::kSeg * F * sizeof(Col4<TA>));
+    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
+    const gptr<int> seglab = as_global((const int *)L->seg_lab) + 4 * (int64_t)segbase;
+    for (int e = lane; e < nseg * F; e += kChunk) {
+        const int sg = e / F, f = e - sg * F;
+        const int ld = seglab[4 * sg], lt = seglab[4 * sg + 1], ls = seglab[4 * sg + 2];
+        const TA pdv = tab[(int64_t)ld * F + f];
+        const TA btv = tab[(kd + 2 * (int64_t)lt) * F + 2 * f];
+        const TA dtv = tab[(kd + 2 * (int64_t)lt) * F + 2 * f + 1];
+        const TA ssv = tab[(kd + 2 * kt + ls) * F + f];
+        Col4<TA> c;
+        c.ad = pdv * btv;
+        c.dt = dtv;
+        c.as = ssv;
+        c.pad = (TA)0;
+        cols[e] = c;
+    }
+    if (SHARED && lane < nseg) {
+        const gptr<double> src = as_global((const double *)a.records) + 16 * (it->part_off + segbase + lane);
+        double *dst = (double *)(recs + lane);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) dst[k] = src[k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    WAcc<TA> A = WAcc<TA>{};
+    SAcc<TA> S[2];
+    S[0] = SAcc<TA>{};
+    S[1] = SAcc<TA>{};
+    const Col4<TA> *mycols = cols + segl * F;
+    auto band = [&](const int f, const TA d0, const TA d1) {
+        const Col4<TA> c = mycols[f];
+        const TA w = Band<TA>::w(B, 0, f);
+        const TA lgd = Band<TA>::ld(B, f), lgs = Band<TA>::ls(B, f);
+        const TA wad = w * c.ad, was = w * c.as;
+        const TA c1 = wad * lgd, c2 = wad * c.dt, c3 = was * lgs;
+        if (!SHARED) {
+            A.m01 += wad;
+            A.m02 += was;
+            A.m11 = fma(wad, c.ad, A.m11);
+            A.m12 = fma(wad, c.as, A.m12);
+            A.m22 = fma(was, c.as, A.m22);
+            if (GRAD) {
+                A.g01 += c1;
+                A.g02 += c2;
+                A.g03 += c3;
+                A.g11 = fma(c1, c.ad, A.g11);
+                A.g12 = fma(c2, c.ad, A.g12);
+                A.g13 = fma(c3, c.ad, A.g13);
+                A.g21 = fma(c1, c.as, A.g21);
+                A.g22 = fma(c2, c.as, A.g22);
+                A.g23 = fma(c3, c.as, A.g23);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const TA dv = s ? d1 : d0;
+            SAcc<TA> &q = S[s];
+            q.b0 = fma(w, dv, q.b0);
+            q.b1 = fma(wad, dv, q.b1);
+            q.b2 = fma(was, dv, q.b2);
+            if (GRAD) {
+                q.h1 = fma(c1, dv, q.h1);
+                q.h2 = fma(c2, dv, q.h2);
+                q.h3 = fma(c3, dv, q.h3);
+            }
+        }
+    };
+    // band loop: consume ring slot r, then refill it kRing groups ahead
+    for (int g0 = 0; g0 < F; g0 += kRing * kG) {
+#pragma unroll
+        for (int r = 0; r < kRing; ++r) {
+            const int fb = g0 + r * kG;
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (fb + j < F) band(fb + j, (TA)rq[r][j], (TA)ru[r][j]);
+            if (fb + kRing * kG < F) {
+#pragma unroll
+                for (int j = 0; j < kG; ++j) {
+                    const int f0 = fb + kRing * kG + j;
+                    const int f = f0 < F ? f0 : F - 1;
+                    rq[r][j] = dq[f * kChunk];
+                    ru[r][j] = du[f * kChunk];
+                }
+            }
+        }
+    }
+
+    // a5/a6: Cholesky factor (per pixel, or the staged segment record), then F and gradient
+    double i00, l10, l20, i11, l21, i22, G[9];
+    bool ok;
+    if (SHARED) {
+        const SegRec &R = recs[segl];
+        i00 = R.i00;
+        l10 = R.l10;
+        l20 = R.l20;
+        i11 = R.i11;
+        l21 = R.l21;
+        i22 = R.i22;
+        G[0] = R.g01; G[1] = R.g02; G[2] = R.g03;
+        G[3] = R.g11; G[4] = R.g12; G[5] = R.g13;
+        G[6] = R.g21; G[7] = R.g22; G[8] = R.g23;
+        ok = R.ok != 0.0;
+    } else {
+        const double m00 = (double)Band<TA>::wsum(B, 0);
+        const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;
+        i00 = 1.0 / sqrt(m00);
+        l10 = m01 * i00;
+        l20 = m02 * i00;
+        const double p1 = m11 - l10 * l10;
+        i11 = 1.0 / sqrt(p1);
+        l21 = (m12 - l20 * l10) * i11;
+        const double p2 = m22 - l20 * l20 - l21 * l21;
+        i22 = 1.0 / sqrt(p2);
+        ok = (m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+        G[0] = A.g01; G[1] = A.g02; G[2] = A.g03;
+        G[3] = A.g11; G[4] = A.g12; G[5] = A.g13;
+        G[6] = A.g21; G[7] = A.g22; G[8] = A.g23;
+    }
+    double fpix = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const SAcc<TA> &q = S[s];
+        const double z0 = (double)q.b0 * i00;
+        const double z1 = ((double)q.b1 - l10 * z0) * i11;
+        const double z2 = ((double)q.b2 - l20 * z0 - l21 * z1) * i22;
+        fpix -= z0 * z0 + z1 * z1 + z2 * z2;
+        if (GRAD) {
+            const double s2 = z2 * i22;
+            const double s1 = (z1 - l21 * s2) * i11;
+            const double s0 = (z0 - l10 * s1 - l20 * s2) * i00;
+            const double e1 = (double)q.h1 - (s0 * G[0] + s1 * G[3] + s2 * G[6]);
+            const double e2 = (double)q.h2 - (s0 * G[1] + s1 * G[4] + s2 * G[7]);
+            const double e3 = (double)q.h3 - (s0 * G[2] + s1 * G[5] + s2 * G[8]);
+            g1 -= 2.0 * s1 * e1;
+            g2 -= 2.0 * s1 * e2;
+            g3 -= 2.0 * s2 * e3;
+        }
+    }
+    if (!valid) {
+        fpix = 0.0;
+        g1 = g2 = g3 = 0.0;
+    } else if (!ok) {
+        fpix = g1 = g2 = g3 = __builtin_nan("");
+    }
+    const uint64_t bad = __ballot(valid && !ok);
+    if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
+    seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (it->part_off + segbase + segl) * 4);
+    // the slice is rewritten by the wavefront's next unit
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename TS, typename TA, bool GRAD, bool SHARED>
+__global__ __launch_bounds__(512) void k_pixel_stage(const EvalArgs a) {
+    extern __shared__ char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = a.waves_per_block;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = logical_block(a.xcd_remap);
+    const cptr<int> units = as_const((const int *)a.units);
+    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA>(a.nfreq);
+    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
+        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
+        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
+        if (a.active && !as_const(a.active)[item]) continue;
+        const cptr<LayoutDev> L = as_const(a.layouts) + (as_const(a.items) + item)->layout;
+        const int nseg = as_const(L->seg_base)[chunk + 1] - as_const(L->seg_base)[chunk];
+        if (nseg <= StageCfg<TA>::kSeg) {
+            unit_staged<TS, TA, GRAD, SHARED>(a, item, chunk, lane, wave_lds);
+        } else if (SHARED) {
+            const int segbase = as_const(L->seg_base)[chunk];
+            unit_seg<TS, TA, GRAD, 0>(a, item, chunk, lane,
+                                      (const SegRec *)a.records + (as_const(a.items) + item)->part_off + segbase);
+        } else {
+            unit_pixel<TS, TA, GRAD, 0, 0>(a, item, chunk, lane);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// a7 (second level): deterministic compensated sums over each cluster's segments
+// ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int64_t ktot, double *grad,
                                                   double *cluster_f) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -667,11 +859,26 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     }
     const int32_t *perm = L.seg_perm[j];
     const int b = L.seg_off[j][r], e = L.seg_off[j][r + 1];
+    const double *part = a.partials + it.part_off * 4;
     double gs = 0, gc = 0, fs = 0, fc = 0;
-    for (int i = b; i < e; ++i) {
-        const double *q = a.partials + (it.part_off + perm[i]) * 4;
-        if (grad) neu_add(gs, gc, q[1 + j]);
-        if (cluster_f) neu_add(fs, fc, q[0]);
+    // segments are scattered in the partials: request kB of them at a time, then add in order
+    constexpr int kB = 8;
+    for (int i0 = b; i0 < e; i0 += kB) {
+        int idx[kB];
+        double vg[kB], vf[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) idx[k] = (i0 + k < e) ? perm[i0 + k] : perm[b];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            vg[k] = part[idx[k] * 4 + 1 + j];
+            vf[k] = part[idx[k] * 4];
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+            if (i0 + k < e) {
+                if (grad) neu_add(gs, gc, vg[k]);
+                if (cluster_f) neu_add(fs, fc, vf[k]);
+            }
     }
     if (grad) {
         const double v = gs + gc;
@@ -681,19 +888,32 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     if (cluster_f) cluster_f[g] = fs + fc;
 }
 
-__global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
+constexpr int kFinThreads = 1024;
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
     const int item = blockIdx.x;
     if (a.active && !a.active[item]) return;
     const ItemDev &it = a.items[item];
     const LayoutDev &L = a.layouts[it.layout];
     const int n = L.nseg;
+    const double *part = a.partials + it.part_off * 4;
     double s = 0, c = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) neu_add(s, c, a.partials[(it.part_off + i) * 4]);
-    __shared__ double ss[256], sc[256];
+    constexpr int kU = 4;
+    for (int i0 = threadIdx.x; i0 < n; i0 += kU * kFinThreads) {
+        double v[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const int i = i0 + k * kFinThreads;
+            v[k] = i < n ? part[(int64_t)i * 4] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kU; ++k) neu_add(s, c, v[k]);
+    }
+    __shared__ double ss[kFinThreads], sc[kFinThreads];
     ss[threadIdx.x] = s;
     sc[threadIdx.x] = c;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = kFinThreads / 2; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) {
             double s1 = ss[threadIdx.x], c1 = sc[threadIdx.x];
             neu_add(s1, c1, ss[threadIdx.x + st]);
@@ -718,7 +938,14 @@ __global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2log
 // ---------------------------------------------------------------------------------------------
 template <typename TS, typename TA, bool GRAD, int FM>
 static void launch_pixel_f(int wm, bool shared, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    if (wm == 0 && shared)
+    // LDS staging needs stage_bytes_per_wave per wavefront; a workgroup may hold at most 64 KiB
+    const size_t lds = stage_bytes_per_wave<TA>(a.nfreq) * (block.x / kChunk);
+    const bool staged = lds <= 65536;
+    if (wm == 0 && shared && staged)
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, true>), grid, block, lds, s, a);
+    else if (wm == 0 && staged)
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, false>), grid, block, lds, s, a);
+    else if (wm == 0 && shared)
         hipLaunchKernelGGL((k_pixel_seg<TS, TA, GRAD, FM>), grid, block, 0, s, a);
     else if (wm == 0)
         hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, FM>), grid, block, 0, s, a);
@@ -746,8 +973,7 @@ static void launch_pixel_g(bool grad, int wm, bool shared, int F, dim3 grid, dim
         launch_pixel_t<TS, TA, false>(wm, shared, F, grid, block, s, a);
 }
 
-cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
-                      double *cluster_f, int32_t *status, bool want_grad, cs_precision mode, hipStream_t s) {
+EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active) {
     const WsLayout &w = p->ws;
     EvalArgs a;
     a.units = (const int2 *)(p->wsp + w.units);
@@ -767,16 +993,32 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     a.nfreq = p->F;
     a.xcd_remap = p->sched.xcd_remap;
     a.waves_per_block = p->sched.waves_per_block;
+    return a;
+}
+
+cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s) {
+    const int64_t ktot = p->xoff[p->B];
+    const int64_t *xoff_dev = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)p->B);
+    const unsigned sblocks = (unsigned)((ktot * p->F + 255) / 256);
+    if (fp32_tables)
+        hipLaunchKernelGGL(k_sed<float>, dim3(sblocks), dim3(256), 0, s, a, xoff_dev, ktot);
+    else
+        hipLaunchKernelGGL(k_sed<double>, dim3(sblocks), dim3(256), 0, s, a, xoff_dev, ktot);
+    CSI_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
+                      double *cluster_f, int32_t *status, bool want_grad, cs_precision mode, hipStream_t s) {
+    const WsLayout &w = p->ws;
+    const EvalArgs a = make_eval_args(p, x, active);
     const int64_t ktot = p->xoff[p->B];
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
     const bool t32 = (mode == CS_FP32_BULK);
     const unsigned kblocks = (unsigned)((ktot + 255) / 256);
 
-    if (t32)
-        hipLaunchKernelGGL(k_sed<float>, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot);
-    else
-        hipLaunchKernelGGL(k_sed<double>, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot);
-    CSI_HIP(hipGetLastError());
+    const cs_status sst = launch_sed(p, a, t32, s);
+    if (sst != CS_OK) return sst;
 
     const int wpb = p->sched.waves_per_block;
     int64_t nblocks = (p->nunits + wpb - 1) / wpb;
@@ -825,7 +1067,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
                            cluster_f);
         CSI_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_fin_f, dim3(p->B), dim3(256), 0, s, a, neg2logl, status);
+    hipLaunchKernelGGL(k_fin_f, dim3(p->B), dim3(kFinThreads), 0, s, a, neg2logl, status);
     CSI_HIP(hipGetLastError());
     return CS_OK;
 }

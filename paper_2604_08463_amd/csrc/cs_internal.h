@@ -141,13 +141,29 @@ cs_status hip_fail(hipError_t e, const char *what);
 // a1: segment preparation (cs_prep.hip)
 cs_status prepare_layouts(cs_problem *p, hipStream_t s);
 cs_status pack_data(cs_problem *p, hipStream_t s);
+// Ascending bitonic sort of nlayouts arrays of n keys (n a power of two >= 2048) spaced lstride
+// apart; layouts with active_layout[l] == 0 are skipped (active_layout nullable).
+cs_status bitonic_sort(uint64_t *base, int64_t lstride, int64_t n, int nlayouts, const int32_t *active_layout,
+                       hipStream_t s);
 cs_status export_segments(cs_problem *p, int32_t item, int32_t j, int32_t *perm, int32_t *offsets,
                           hipStream_t s);
 
 // a2-a7: one batched evaluation (cs_eval.hip)
+EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active);
+cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s);
 cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl,
                       double *grad, double *cluster_f, int32_t *status, bool want_grad,
                       cs_precision mode, hipStream_t s);
+
+// component maps and the CMB map variance (cs_maps.hip)
+cs_status launch_maps(cs_problem *p, const double *x, double *maps, int64_t maps_stride, double *cmb_var,
+                      int32_t *status, hipStream_t s);
+
+// spherical K-means patching (cs_kmeans.hip)
+size_t kmeans_bytes(int64_t n, int32_t ntasks, int64_t ktot);
+cs_status kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep, int64_t keep_stride,
+                       const int32_t *k_host, const int32_t *init, int64_t init_stride, int32_t iters,
+                       int32_t *labels, int64_t labels_stride, int32_t *keff, void *ws, hipStream_t s);
 
 // a8: batched projected L-BFGS (cs_optim.hip)
 size_t optimizer_bytes(const cs_problem *p, int32_t m);

@@ -1,0 +1,215 @@
+// Component maps and the CMB map variance at given spectral parameters.
+//
+// The generalised least-squares amplitudes of one pixel and Stokes parameter are
+// s_hat = (A^T N^-1 A)^-1 A^T N^-1 d (paper Sec. 2.3, the reconstruction operator W applied to
+// the data).  The CMB variance metric used to choose the number of clusters is the variance of
+// the reconstructed CMB amplitude over the analysis mask, here the population variance of Q plus
+// that of U (Sec. 2.4, eq. min_var).
+//
+//   k_fill_nan  every map element of the requested items := NaN (excluded pixels stay NaN)
+//   k_maps      one wavefront per 64-pixel chunk: FP64 normal equations from the stored data,
+//               Cholesky, s_hat written in the caller's pixel order, and the chunk's
+//               (count, mean, centred sum of squares) of the Q and U CMB amplitudes
+//   k_maps_var  one workgroup per item: pairwise combination of the chunk moments
+//               (Chan, Golub & LeVeque's update), variance and status word
+#include "cs_device.h"
+
+namespace csi {
+
+namespace {
+
+constexpr int kMapWaves = 4;
+constexpr int kVarThreads = 256;
+
+struct Moments {  // count, then (mean, centred sum of squares) of Q and of U
+    double n, mq, sq, mu, su;
+};
+
+__device__ __forceinline__ Moments combine(const Moments &a, const Moments &b) {
+    if (b.n == 0.0) return a;
+    if (a.n == 0.0) return b;
+    Moments r;
+    r.n = a.n + b.n;
+    const double fb = b.n / r.n, fab = a.n * b.n / r.n;
+    const double dq = b.mq - a.mq, du = b.mu - a.mu;
+    r.mq = a.mq + dq * fb;
+    r.sq = a.sq + b.sq + dq * dq * fab;
+    r.mu = a.mu + du * fb;
+    r.su = a.su + b.su + du * du * fab;
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_nan(double *maps, int64_t stride, int64_t per_item, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t b = i / per_item;
+    maps[b * stride + (i - b * per_item)] = __builtin_nan("");
+}
+
+template <typename TS>
+__global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const int wm, double *maps,
+                                                          const int64_t stride, const int32_t npix) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * kMapWaves + (threadIdx.x >> 6);
+    if (u >= a.nunits) return;
+    const int item = __builtin_amdgcn_readfirstlane(a.units[u].x);
+    const int chunk = __builtin_amdgcn_readfirstlane(a.units[u].y);
+    const int F = a.nfreq;
+    const ItemDev &it = a.items[item];
+    const LayoutDev &L = a.layouts[it.layout];
+    const uint64_t head = L.head[chunk];
+    const int segbase = L.seg_base[chunk];
+    const int nvalid = min(L.n_incl - chunk * kChunk, kChunk);
+    const bool valid = lane < nvalid;
+    const int seg = segbase + __popcll(head & lanemask_le(lane)) - 1;
+    const int *lab = (const int *)L.seg_lab + 4 * (int64_t)seg;
+    const int64_t kd = it.k[0], kt = it.k[1];
+    const double *tab = (const double *)a.tables + it.tab_off * (int64_t)F;
+    const double *pd = tab + (int64_t)lab[0] * F;
+    const double *bt = tab + (kd + 2 * (int64_t)lab[1]) * F;
+    const double *ss = tab + (kd + 2 * kt + lab[2]) * F;
+    const int64_t cbase = (it.dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+    const TS *dq = (const TS *)a.dpack + cbase;
+    const TS *wq = (wm == 2) ? (const TS *)a.wpack + cbase : nullptr;
+    const BandDev &B = *a.band;
+
+    // normal equations per Stokes parameter: M (upper triangle) and b, in FP64
+    double m[2][6], b[2][3];
+    for (int s = 0; s < 2; ++s) {
+        for (int i = 0; i < 6; ++i) m[s][i] = 0.0;
+        for (int i = 0; i < 3; ++i) b[s][i] = 0.0;
+    }
+    for (int f = 0; f < F; ++f) {
+        const double ad = pd[f] * bt[2 * f], as = ss[f];
+        for (int s = 0; s < 2; ++s) {
+            const int64_t o = ((int64_t)s * F + f) * kChunk;
+            const double w = (wm == 2) ? (double)wq[o] : B.w[s][f];
+            const double dv = (double)dq[o];
+            const double wad = w * ad, was = w * as;
+            m[s][0] += w;
+            m[s][1] += wad;
+            m[s][2] += was;
+            m[s][3] += wad * ad;
+            m[s][4] += wad * as;
+            m[s][5] += was * as;
+            b[s][0] += w * dv;
+            b[s][1] += wad * dv;
+            b[s][2] += was * dv;
+        }
+    }
+    double sh[2][3];
+    bool ok = true;
+    for (int s = 0; s < 2; ++s) {
+        const double *c = m[s];
+        const double l00 = sqrt(c[0]);
+        const double l10 = c[1] / l00, l20 = c[2] / l00;
+        const double p1 = c[3] - l10 * l10;
+        const double l11 = sqrt(p1);
+        const double l21 = (c[4] - l20 * l10) / l11;
+        const double p2 = c[5] - l20 * l20 - l21 * l21;
+        const double l22 = sqrt(p2);
+        ok = ok && (c[0] > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+        const double z0 = b[s][0] / l00;
+        const double z1 = (b[s][1] - l10 * z0) / l11;
+        const double z2 = (b[s][2] - l20 * z0 - l21 * z1) / l22;
+        sh[s][2] = z2 / l22;
+        sh[s][1] = (z1 - l21 * sh[s][2]) / l11;
+        sh[s][0] = (z0 - l10 * sh[s][1] - l20 * sh[s][2]) / l00;
+    }
+    if (!ok)
+        for (int s = 0; s < 2; ++s)
+            for (int c = 0; c < 3; ++c) sh[s][c] = __builtin_nan("");
+    if (__ballot(valid && !ok) && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
+
+    if (maps && valid) {
+        const int32_t pix = L.order[chunk * kChunk + lane];
+        double *o = maps + (int64_t)item * stride + pix;
+        for (int s = 0; s < 2; ++s)
+            for (int c = 0; c < 3; ++c) o[(int64_t)(3 * s + c) * npix] = sh[s][c];
+    }
+
+    // chunk moments of the CMB amplitude (NaN propagates from a non-positive-definite pixel)
+    const double n = (double)nvalid;
+    const double vq = valid ? sh[0][0] : 0.0, vu = valid ? sh[1][0] : 0.0;
+    const double mq = wave_sum(vq) / n, mu = wave_sum(vu) / n;
+    const double eq = valid ? vq - mq : 0.0, eu = valid ? vu - mu : 0.0;
+    const double sq = wave_sum(eq * eq), su = wave_sum(eu * eu);
+    if (lane == 0) {
+        double *st = a.partials + it.part_off * 4 + (int64_t)chunk * 8;
+        st[0] = n;
+        st[1] = mq;
+        st[2] = sq;
+        st[3] = mu;
+        st[4] = su;
+    }
+}
+
+__global__ __launch_bounds__(kVarThreads) void k_maps_var(const EvalArgs a, double *cmb_var, int32_t *status) {
+    const int item = blockIdx.x;
+    const ItemDev &it = a.items[item];
+    const LayoutDev &L = a.layouts[it.layout];
+    const int64_t nc = L.nchunks;
+    const double *st = a.partials + it.part_off * 4;
+    // thread t folds the contiguous chunk range [t nc / T, (t + 1) nc / T) in order
+    const int t = threadIdx.x;
+    Moments acc{0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = t * nc / kVarThreads; c < (t + 1) * nc / kVarThreads; ++c) {
+        const double *r = st + c * 8;
+        acc = combine(acc, Moments{r[0], r[1], r[2], r[3], r[4]});
+    }
+    __shared__ Moments sm[kVarThreads];
+    sm[t] = acc;
+    __syncthreads();
+    for (int h = kVarThreads / 2; h > 0; h >>= 1) {
+        if (t < h) sm[t] = combine(sm[t], sm[t + h]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        int s = a.istatus[item];
+        const Moments r = sm[0];
+        double v = r.n > 0.0 ? r.sq / r.n + r.su / r.n : __builtin_nan("");
+        if (s & CS_ITEM_NOT_PD)
+            v = __builtin_nan("");
+        else if (!isfinite(v) && r.n > 0.0)
+            s |= CS_ITEM_NONFINITE;
+        if (cmb_var) cmb_var[item] = v;
+        if (status) status[item] = s;
+        a.istatus[item] = s;
+    }
+}
+
+}  // namespace
+
+cs_status launch_maps(cs_problem *p, const double *x, double *maps, int64_t maps_stride, double *cmb_var,
+                      int32_t *status, hipStream_t s) {
+    const EvalArgs a = make_eval_args(p, x, nullptr);
+    cs_status st = launch_sed(p, a, false, s);  // FP64 tables (also resets the status words)
+    if (st != CS_OK) return st;
+    const int64_t per_item = 6 * (int64_t)p->P;
+    if (maps) {
+        const int64_t total = per_item * p->B;
+        hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, maps, maps_stride,
+                           per_item, total);
+        CSI_HIP(hipGetLastError());
+    }
+    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : 1;
+    if (p->nunits > 0) {
+        const dim3 grid((unsigned)((p->nunits + kMapWaves - 1) / kMapWaves)), block(64 * kMapWaves);
+        if (p->prec == CS_FP64)
+            hipLaunchKernelGGL(k_maps<double>, grid, block, 0, s, a, wm, maps, maps_stride, p->P);
+        else
+            hipLaunchKernelGGL(k_maps<float>, grid, block, 0, s, a, wm, maps, maps_stride, p->P);
+        CSI_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_maps_var, dim3(p->B), dim3(kVarThreads), 0, s, a, cmb_var, status);
+    CSI_HIP(hipGetLastError());
+    return CS_OK;
+}
+
+}  // namespace csi

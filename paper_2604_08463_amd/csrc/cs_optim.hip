@@ -12,6 +12,8 @@
 // The direction is the two-loop recursion restricted to the free set (variables not held at a
 // bound by the sign of their gradient).  Items that finish are masked out of the evaluation
 // kernels through active[].  The host reads one counter after each replay.
+#include <algorithm>
+
 #include "cs_internal.h"
 
 namespace csi {
@@ -40,40 +42,47 @@ struct OptArgs {
     double gtol, c1;
 };
 
-constexpr int kOptThreads = 256;
+constexpr int kOptThreads = 256;   // block size of the small per-item kernels
 constexpr double kFlatRel = 1e-12;  // relative change of F below which Armijo is not resolved
 
-// deterministic block sum of N values (fixed shuffle tree, then waves in order)
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[kOptThreads / 64]) {
+// deterministic block sum of N values (fixed shuffle tree, then the waves in order)
+template <int N, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[16]) {
+    constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int n = 0; n < N; ++n) {
         double x = v[n];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) sh[n][wave] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        double x = 0;
-#pragma unroll
-        for (int w = 0; w < kOptThreads / 64; ++w) x += sh[n][w];
         v[n] = x;
+        if (NWV > 1 && lane == 0) sh[n][wave] = x;
     }
-    __syncthreads();
+    if (NWV > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            double x = 0;
+#pragma unroll
+            for (int w = 0; w < NWV; ++w) x += sh[n][w];
+            v[n] = x;
+        }
+        __syncthreads();
+    }
 }
 
+template <int NT>
 __device__ __forceinline__ double block_max(double v, double *sh) {
+    constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if (NWV == 1) return v;
     if (lane == 0) sh[wave] = v;
     __syncthreads();
     double x = sh[0];
 #pragma unroll
-    for (int w = 1; w < kOptThreads / 64; ++w) x = fmax(x, sh[w]);
+    for (int w = 1; w < NWV; ++w) x = fmax(x, sh[w]);
     __syncthreads();
     return x;
 }
@@ -102,13 +111,17 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_init(OptArgs a, const doubl
     }
 }
 
-__global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
+// One optimiser step per active item (one workgroup of NT threads per item).  The two-loop
+// recursion runs as fused passes over the item's vectors: the pass for pair j first applies the
+// previous pair's update, then forms pair j's products, so each pair costs one pass per loop.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
     const int item = blockIdx.x;
     if (!a.active[item]) return;
-    __shared__ double red[8][kOptThreads / 64];
+    __shared__ double red[8][16];
     __shared__ double rho[32], alp[32];
     const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
     double *y = a.y + o, *g = a.g + o, *p = a.p + o, *yt = a.yt + o, *xt = a.xt + o;
     OptItem s = a.st[item];  // every thread holds the same copy
@@ -125,17 +138,19 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
             if (!finish) finish = CS_ITEM_NONFINITE;
         } else {
             double v[1] = {0.0};
-            for (int64_t i = tid; i < K; i += nt) {
+            for (int64_t i = tid; i < K; i += NT) {
                 const double gi = ge[i] * (hi[i] - lo[i]);
                 g[i] = gi;
                 if (is_free(y[i], gi)) v[0] += gi * gi;
             }
-            block_sum<1>(v, red);
+            block_sum<1, NT>(v, red);
             s.f = fe;
             if (s.state == ST_INIT) {
                 s.pg0 = sqrt(v[0]);
-                if (!isfinite(s.pg0)) finish = CS_ITEM_NONFINITE;
-                else if (s.pg0 == 0.0) finish = CS_ITEM_CONVERGED;
+                if (!isfinite(s.pg0))
+                    finish = CS_ITEM_NONFINITE;
+                else if (s.pg0 == 0.0)
+                    finish = CS_ITEM_CONVERGED;
             }
             if (!finish && s.iter >= a.max_iter) finish = CS_ITEM_MAXITER;
             need_dir = !finish;
@@ -144,7 +159,7 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
         // s = yt - y, t = g_trial - g (internal gradients): s.t, s.s, t.t and g_trial.s
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (evalok) {
-            for (int64_t i = tid; i < K; i += nt) {
+            for (int64_t i = tid; i < K; i += NT) {
                 const double si = yt[i] - y[i], gti = ge[i] * (hi[i] - lo[i]), ti = gti - g[i];
                 v[0] += si * ti;
                 v[1] += si * si;
@@ -152,7 +167,7 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
                 v[3] += gti * si;
             }
         }
-        block_sum<4>(v, red);
+        block_sum<4, NT>(v, red);
         // Armijo, or (at the rounding floor of F) F unchanged and still non-increasing at the trial
         const bool flat = fabs(fe - s.f) <= kFlatRel * fabs(s.f) && v[3] <= 0.0;
         if (evalok && v[1] > 0.0 && (fe <= s.f + a.c1 * s.dec || flat)) {  // never accept a null step
@@ -160,7 +175,7 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
             const int nw = keep ? (s.newest + 1) % a.m : s.newest;
             double *Sn = a.S + (int64_t)nw * a.ktot + o, *Tn = a.T + (int64_t)nw * a.ktot + o;
             double pg[1] = {0.0};
-            for (int64_t i = tid; i < K; i += nt) {
+            for (int64_t i = tid; i < K; i += NT) {
                 const double gi = ge[i] * (hi[i] - lo[i]);
                 if (keep) {
                     Sn[i] = yt[i] - y[i];
@@ -170,7 +185,7 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
                 g[i] = gi;
                 if (is_free(yt[i], gi)) pg[0] += gi * gi;
             }
-            block_sum<1>(pg, red);
+            block_sum<1, NT>(pg, red);
             if (keep) {
                 s.newest = nw;
                 if (s.npairs < a.m) s.npairs += 1;
@@ -184,35 +199,47 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
             need_dir = !finish;
         } else {
             s.nbt += 1;
-            if (s.nbt > a.max_backtracks) {
+            if (s.nbt > a.max_backtracks)
                 finish = CS_ITEM_LS_FAIL;
-            } else {
+            else
                 s.alpha *= 0.5;
-            }
         }
     }
 
     if (need_dir) {
-        // q = P g on the free set (kept in p), two-loop recursion restricted to the free set
+        // Two-loop recursion on the free set, q = P g held in p.  Backward (newest pair first):
+        // the pass of pair j applies the pending q -= alpha t of the previous used pair, then forms
+        // the masked s.t, s.s, t.t and s.q of pair j.  Forward (oldest first): the pass of pair j
+        // applies gamma (first pass) and the pending r += s (alpha - beta), then forms t.r.
         const int np = s.npairs, m = a.m;
-        for (int64_t i = tid; i < K; i += nt) p[i] = is_free(y[i], g[i]) ? g[i] : 0.0;
         double gamma = 1.0;
         bool gamma_set = false;
         int used = 0;
+        bool qinit = false;            // p holds q
+        const double *pendT = nullptr;  // pending backward update
+        double penda = 0.0;
         for (int c = 0; c < np; ++c) {
             const int j = ((s.newest - c) % m + m) % m;
             const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
-            double v[3] = {0.0, 0.0, 0.0};
-            for (int64_t i = tid; i < K; i += nt)
-                if (is_free(y[i], g[i])) {
-                    v[0] += Sj[i] * Tj[i];
-                    v[1] += Sj[i] * Sj[i];
-                    v[2] += Tj[i] * Tj[i];
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t i = tid; i < K; i += NT) {
+                const bool fr = is_free(y[i], g[i]);
+                double q = qinit ? p[i] : (fr ? g[i] : 0.0);
+                if (pendT && fr) q -= penda * pendT[i];
+                if (!qinit || pendT) p[i] = q;
+                if (fr) {
+                    const double si = Sj[i], ti = Tj[i];
+                    v[0] += si * ti;
+                    v[1] += si * si;
+                    v[2] += ti * ti;
+                    v[3] += si * q;
                 }
-            block_sum<3>(v, red);
+            }
+            block_sum<4, NT>(v, red);
+            qinit = true;
+            pendT = nullptr;
             if (!(v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2])) || v[2] == 0.0) {
                 if (tid == 0) rho[j] = 0.0;
-                __syncthreads();
                 continue;
             }
             const double rj = 1.0 / v[0];
@@ -220,56 +247,72 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
                 gamma = v[0] / v[2];
                 gamma_set = true;
             }
-            double sq[1] = {0.0};
-            for (int64_t i = tid; i < K; i += nt)
-                if (is_free(y[i], g[i])) sq[0] += Sj[i] * p[i];
-            block_sum<1>(sq, red);
-            const double aj = rj * sq[0];
-            for (int64_t i = tid; i < K; i += nt)
-                if (is_free(y[i], g[i])) p[i] -= aj * Tj[i];
+            const double aj = rj * v[3];
             if (tid == 0) {
                 rho[j] = rj;
                 alp[j] = aj;
             }
-            __syncthreads();
+            pendT = Tj;
+            penda = aj;
             ++used;
         }
-        for (int64_t i = tid; i < K; i += nt) p[i] *= gamma;
-        __syncthreads();
+        __syncthreads();  // rho / alp visible to every thread
+        bool scaled = false;            // gamma applied
+        const double *pendS = nullptr;  // pending forward update
+        double pendc = 0.0;
         for (int c = np - 1; c >= 0; --c) {
             const int j = ((s.newest - c) % m + m) % m;
             const double rj = rho[j];
             if (rj == 0.0) continue;
             const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
-            double tq[1] = {0.0};
-            for (int64_t i = tid; i < K; i += nt)
-                if (is_free(y[i], g[i])) tq[0] += Tj[i] * p[i];
-            block_sum<1>(tq, red);
-            const double be = rj * tq[0];
-            const double aj = alp[j];
-            for (int64_t i = tid; i < K; i += nt)
-                if (is_free(y[i], g[i])) p[i] += Sj[i] * (aj - be);
-            __syncthreads();
+            double v[1] = {0.0};
+            for (int64_t i = tid; i < K; i += NT) {
+                const bool fr = is_free(y[i], g[i]);
+                double r = p[i];
+                if (!scaled) {
+                    if (pendT && fr) r -= penda * pendT[i];
+                    r *= gamma;
+                }
+                if (pendS && fr) r += pendS[i] * pendc;
+                p[i] = r;
+                if (fr) v[0] += Tj[i] * r;
+            }
+            block_sum<1, NT>(v, red);
+            scaled = true;
+            pendT = nullptr;
+            pendS = Sj;
+            pendc = alp[j] - rj * v[0];
         }
-        // p = -H Pg on the free set; fall back to -Pg when not a finite descent direction
+        // final pass: remaining pending updates, p = -(H P g) on the free set, p.g, max |p|
         double v[2] = {0.0, 0.0};
-        for (int64_t i = tid; i < K; i += nt) {
-            const double pi = is_free(y[i], g[i]) ? -p[i] : 0.0;
+        double pm = 0.0;
+        for (int64_t i = tid; i < K; i += NT) {
+            const bool fr = is_free(y[i], g[i]);
+            double r = qinit ? p[i] : (fr ? g[i] : 0.0);
+            if (!scaled) {
+                if (pendT && fr) r -= penda * pendT[i];
+                r *= gamma;
+            }
+            if (pendS && fr) r += pendS[i] * pendc;
+            const double pi = fr ? -r : 0.0;
             p[i] = pi;
             v[0] += pi * g[i];
             v[1] += isfinite(pi) ? 0.0 : 1.0;
+            pm = fmax(pm, fabs(pi));
         }
-        block_sum<2>(v, red);
-        if (!(v[0] < 0.0) || v[1] != 0.0) {
+        block_sum<2, NT>(v, red);
+        if (!(v[0] < 0.0) || v[1] != 0.0) {  // not a finite descent direction: clear memory, -Pg
             s.npairs = 0;
             s.newest = -1;
             used = 0;
-            for (int64_t i = tid; i < K; i += nt) p[i] = is_free(y[i], g[i]) ? -g[i] : 0.0;
-            __syncthreads();
+            pm = 0.0;
+            for (int64_t i = tid; i < K; i += NT) {
+                const double pi = is_free(y[i], g[i]) ? -g[i] : 0.0;
+                p[i] = pi;
+                pm = fmax(pm, fabs(pi));
+            }
         }
-        double pm = 0.0;
-        for (int64_t i = tid; i < K; i += nt) pm = fmax(pm, fabs(p[i]));
-        pm = block_max(pm, red[0]);
+        pm = block_max<NT>(pm, red[0]);
         s.alpha = used ? 1.0 : (pm > 1.0 ? 1.0 / pm : 1.0);
         s.nbt = 0;
     }
@@ -277,14 +320,14 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_update(OptArgs a) {
     if (!finish && s.state != ST_DONE) {
         // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y)
         double v[1] = {0.0};
-        for (int64_t i = tid; i < K; i += nt) {
+        for (int64_t i = tid; i < K; i += NT) {
             double t = y[i] + s.alpha * p[i];
             t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
             yt[i] = t;
             xt[i] = lo[i] + t * (hi[i] - lo[i]);
             v[0] += g[i] * (t - y[i]);
         }
-        block_sum<1>(v, red);
+        block_sum<1, NT>(v, red);
         s.dec = v[0];
         s.state = ST_SEARCH;
     }
@@ -360,6 +403,8 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
                    int32_t *iters, int32_t *status, int64_t *nevals, void *ws, size_t bytes, hipStream_t caller) {
     const int B = p->B;
     const int64_t K = p->xoff[B];
+    int64_t kmax = 0;
+    for (int b = 0; b < B; ++b) kmax = std::max<int64_t>(kmax, p->xoff[b + 1] - p->xoff[b]);
     if (bytes < optimizer_bytes(p, o->m)) {
         set_error("optimizer workspace too small");
         return CS_E_WORKSPACE;
@@ -441,7 +486,10 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
             for (int k = 0; k < o->iters_per_graph && rc == CS_OK; ++k) {
                 rc = launch_eval(p, a.xt, a.active, fe, ge, nullptr, estat, true, mode, s);
                 if (rc == CS_OK) {
-                    hipLaunchKernelGGL(k_opt_update, dim3(B), dim3(kOptThreads), 0, s, a);
+                    if (kmax <= 512)
+                        hipLaunchKernelGGL(k_opt_update<64>, dim3(B), dim3(64), 0, s, a);
+                    else
+                        hipLaunchKernelGGL(k_opt_update<1024>, dim3(B), dim3(1024), 0, s, a);
                     hipError_t eu = hipGetLastError();
                     if (eu != hipSuccess) rc = hip_fail(eu, "k_opt_update");
                 }

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_bitonic_global(uint64_t *base, int64_t 
     }
 }
 
-static cs_status bitonic_sort(uint64_t *base, int64_t lstride, int64_t n, int nlayouts,
+cs_status bitonic_sort(uint64_t *base, int64_t lstride, int64_t n, int nlayouts,
                               const int32_t *active_layout, hipStream_t s) {
     // n is a power of two >= kSortTile
     const int tiles = (int)(n / kSortTile);

@@ -276,3 +276,82 @@ def test_optimizer_fp32_bulk_within_1e4_of_fp64():
     f64, f32 = r64["f"].cpu().numpy(), r32["f"].cpu().numpy()
     assert np.all(np.abs(x32 - x64) <= 1e-4 * np.maximum(1.0, np.abs(x64))), np.max(np.abs(x32 - x64))
     assert np.all(np.abs(f32 - f64) <= TOL_F["fp32_bulk"] * np.abs(f64))
+
+
+# ------------------------------------------------------------------------------------------
+# a9: graph capture, autotuning, ragged configuration scan
+# ------------------------------------------------------------------------------------------
+
+def test_graph_replays_match_eager():
+    sky = skygen.make_config(2, npix=8000, nitems=4, k=(200, 20, 60))
+    prob = cs.Problem.from_sky(sky, "fp32_bulk")
+    x = torch.as_tensor(sky.x_packed(), device="cuda")
+    f_e, g_e, _, st_e = prob.cs_likelihood_grad(x)
+    torch.cuda.synchronize()
+    f_e, g_e = f_e.clone(), g_e.clone()
+    out = (torch.empty_like(f_e), torch.empty_like(g_e), torch.empty_like(st_e))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        prob.cs_likelihood_grad(x, out=out)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        prob.cs_likelihood_grad(x, out=out)
+    for rep in range(4):
+        out[0].fill_(0.0)
+        out[1].fill_(0.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], f_e) and torch.equal(out[1], g_e), rep
+        # eager work between replays
+        prob.cs_likelihood_grad(x + 0.01 * rep)
+        torch.cuda.synchronize()
+
+
+def test_autotune_returns_valid_schedule():
+    sky = skygen.make_config(2, npix=12000, nitems=4, k=(300, 30, 80))
+    prob = cs.Problem.from_sky(sky, "fp64")
+    f0, g0, _, _ = gpu_eval(prob, sky, cluster=False)
+    s = prob.autotune(torch.as_tensor(sky.x_packed(), device="cuda"), reps=2)
+    assert s.waves_per_block in (1, 2, 4, 8) and s.blocks_per_cu in (0, 2, 4) and s.xcd_remap in (0, 1)
+    f1, g1, _, _ = gpu_eval(prob, sky, cluster=False)
+    assert np.all(np.abs(f1 - f0) <= 1e-12 * np.abs(f0))
+    compare(sky, prob, "fp64")
+
+
+def test_configuration_scan_optimum_matches_oracle():
+    # ragged labellings, masks and cluster counts per item; the per-configuration minimum of
+    # -2 ln L is the workload's result
+    sky = skygen.make_config(4, nitems=6, kmax4=(60, 12, 20))
+    _log(f"configuration scan: K per item {sky.nclusters.tolist()}")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = prob.cs_optimize_batch(lo, hi, sky.x_packed())
+    f = r["f"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    x = r["x"].cpu().numpy()
+    off = sky.param_offsets()
+    for b in range(sky.nitems):
+        po = oracle.Problem.from_sky(sky, b)
+        xo, fo, it, ne, so = po.lbfgs(sky.x[b], sky.lower[b], sky.upper[b])
+        _log(f"  item {b}: gpu F {f[b]:.10f} st {st[b]}  oracle F {fo:.10f} st {so} it {it}")
+        assert st[b] & cs.CONVERGED and so & oracle.CONVERGED
+        # both reach the same minimum value; the GPU point is a KKT point of the oracle's F
+        assert abs(f[b] - fo) <= 1e-9 * abs(fo)
+        fx, gx, _, _ = po.likelihood_grad(x[off[b]:off[b + 1]])
+        assert abs(fx - f[b]) <= 1e-11 * abs(fx)
+
+
+def test_fp32_bulk_optimum_within_1e4_reduced_workload5():
+    sky = skygen.make_config(5, npix=16384, nitems=4, k=(400, 40, 160))
+    _log("optimizer fp32_bulk vs fp64, reduced workload 5 (16384 px, 22 bands, 600 params)")
+    lo, hi = sky.bounds_packed()
+    r64 = cs.Problem.from_sky(sky, "fp64").cs_optimize_batch(lo, hi, sky.x_packed())
+    r32 = cs.Problem.from_sky(sky, "fp32_bulk").cs_optimize_batch(lo, hi, sky.x_packed())
+    x64, x32 = r64["x"].cpu().numpy(), r32["x"].cpu().numpy()
+    st64, st32 = r64["status"].cpu().numpy(), r32["status"].cpu().numpy()
+    _log(f"  status fp64 {st64.tolist()} fp32 {st32.tolist()} iters {r64['iters'].tolist()} {r32['iters'].tolist()}")
+    _log(f"  max |x32 - x64| {np.max(np.abs(x32 - x64)):.3e}")
+    assert np.all(st64 & cs.CONVERGED)
+    assert np.all(np.abs(x32 - x64) <= 1e-4 * np.maximum(1.0, np.abs(x64)))

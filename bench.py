@@ -16,6 +16,7 @@ around every launch of that kernel in the timed region), and the FP64 oracle on 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pixel_stage_workload5_fp32_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2604_08463_amd", "csrc", "cs_eval.hip")
 
 
 def log(msg):
@@ -46,6 +49,23 @@ def algorithmic_bytes(prob, sky, storage_bytes: int) -> float:
         total += (kd + 2 * kt + ks) * F * storage_bytes
         total += nseg * 4 * 8
     return total
+
+
+def measured_traffic(schedule):
+    """HBM bytes per launch of the pixel kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy's readings), or None unless that summary was taken on the
+    current kernel source and the same kernel variant (per-pixel or segment-shared sums)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SOURCE, "rb") as fh:
+            src = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    shared = int(bool(schedule and schedule.get("shared_segments")))
+    if rec.get("kernel_source_sha256") != src or rec.get("shared_segments") != shared:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def time_eval(prob, x, steps, warmup, timing=True):
@@ -99,6 +119,8 @@ def main():
     ap.add_argument("--precision", default="fp32_bulk", choices=["fp64", "fp32_bulk", "fp32_store"])
     ap.add_argument("--shared-segments", type=int, default=None, choices=[0, 1],
                     help="profiling run: force the per-pixel (0) or segment-shared (1) schedule")
+    ap.add_argument("--schedule", default=None,
+                    help="waves_per_block,blocks_per_cu,xcd_remap,shared_segments (skips the autotuner)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="HBM counter calibration: time a plain device copy of this many bytes and exit")
     args = ap.parse_args()
@@ -136,9 +158,16 @@ def main():
     x = torch.as_tensor(xs, device="cuda")
     x_items = [xs[o:e] for o, e in zip(sky.param_offsets()[:-1], sky.param_offsets()[1:])]
 
+    fixed = None
+    if args.schedule:
+        w, b, xr, sh = (int(v) for v in args.schedule.split(","))
+        fixed = dict(waves_per_block=w, blocks_per_cu=b, xcd_remap=xr, shared_segments=sh)
+
     if args.profile:
         prob = cs.Problem.from_sky(sky, args.precision)
-        if args.shared_segments is not None:
+        if fixed:
+            prob.set_schedule(**fixed)
+        elif args.shared_segments is not None:
             prob.set_schedule(4, 0, 1, args.shared_segments)
         wall, kms, nl, _ = time_eval(prob, x, args.steps, args.warmup)
         ab = algorithmic_bytes(prob, sky, 8 if args.precision == "fp64" else 4)
@@ -153,10 +182,13 @@ def main():
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - tp) * 1e3
     log(f"prepared fp32_bulk problem in {prep_ms:.1f} ms; units={p32.item_info(0)}")
-    sched = None
-    if not args.no_autotune:
+    sched = fixed
+    if fixed:
+        p32.set_schedule(**fixed)
+    elif not args.no_autotune:
         s = p32.autotune(x, reps=3)
-        sched = dict(waves_per_block=s.waves_per_block, blocks_per_cu=s.blocks_per_cu, xcd_remap=s.xcd_remap)
+        sched = dict(waves_per_block=s.waves_per_block, blocks_per_cu=s.blocks_per_cu, xcd_remap=s.xcd_remap,
+                     shared_segments=s.shared_segments)
         log(f"autotuned schedule {sched}")
     wall, kms, nl, out32 = time_eval(p32, x, args.steps, args.warmup)
     f32 = out32[0].cpu().numpy()
@@ -176,7 +208,9 @@ def main():
         del p32
         torch.cuda.empty_cache()
         p64 = cs.Problem.from_sky(sky, "fp64")
-        if sched:
+        if fixed:
+            p64.set_schedule(**fixed)
+        elif sched:
             p64.autotune(x, reps=2)
         w64, k64, n64, out64 = time_eval(p64, x, args.steps, args.warmup)
         f64 = out64[0].cpu().numpy()
@@ -235,9 +269,10 @@ def main():
                    "npix": sky.npix, "nfreq": sky.nfreq, "items": sky.nitems,
                    "clusters": sky.nclusters[0].tolist(), "schedule": sched},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pixel (fused likelihood + adjoint)", "kernel_ms": kavg,
-                     "bytes_per_launch": abytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched),
+                     "kernel": "k_pixel_stage (fused likelihood + adjoint, "
+                               + ("segment-shared" if sched and sched.get("shared_segments") else "per-pixel")
+                               + " sums)", "kernel_ms": kavg, "bytes_per_launch": abytes},
         "cpu_baseline": cpu,
         "fp64_path": fp64,
         "fp32_vs_fp64": err,

@@ -75,7 +75,6 @@ static void carve(cs_problem *p) {
     w.wpack = take(p->nmode == CS_NINV_PIXEL ? elem * 2 * (size_t)p->F * kChunk * w.nchunk_max * B : 0);
     w.tables = take(sizeof(double) * (size_t)p->F * (size_t)p->taboff[p->B]);
     w.partials = take(sizeof(double) * 4 * w.p64 * B);
-    w.records = take(sizeof(double) * 16 * w.p64 * B);
     w.segoff = take(sizeof(int64_t) * (B + 1));
     w.istatus = take(sizeof(int32_t) * B);
     w.total = off;
@@ -202,6 +201,7 @@ cs_status cs_problem_create(const cs_problem_desc *d, cs_problem **out) {
     for (int b = 0; b < p->B; ++b) {
         const int64_t kd = p->ncl[3 * b], kt = p->ncl[3 * b + 1], ks = p->ncl[3 * b + 2];
         p->xoff[b + 1] = p->xoff[b] + kd + kt + ks;
+        p->kmax_item = std::max<int64_t>(p->kmax_item, kd + kt + ks);
         p->taboff[b + 1] = p->taboff[b] + kd + 2 * kt + ks;
     }
     carve(p);

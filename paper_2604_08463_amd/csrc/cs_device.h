@@ -22,18 +22,6 @@ __device__ __forceinline__ gptr<T> as_global(const T *p) {
     return (gptr<T>)p;
 }
 
-__device__ __forceinline__ int find_item(const int64_t *off, int nitems, int64_t g) {
-    int lo = 0, hi = nitems;  // largest lo with off[lo] <= g
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= g)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ uint64_t lanemask_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }

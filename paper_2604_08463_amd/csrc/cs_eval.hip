@@ -50,20 +50,22 @@ struct Band<float> {
 // BTDT[K_T][F][2] = ((nu/nu0d) expm1(x0)/expm1(x) g(nu)/g(nu0d),  d ln(.)/dT);
 // SS[K_s][F] = (nu/nu0s)^beta_s g(nu)/g(nu0s).  The dust column is PD * BT (eq. mixing_columns).
 // ---------------------------------------------------------------------------------------------
+// Grid: x over an item's (parameter, band) pairs, y over items (from item0): the item is uniform
+// in a workgroup, so its descriptor comes through the scalar cache.
 template <typename TT>
-__global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int64_t ktot) {
+__global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int item0) {
     const int F = a.nfreq;
+    const int item = item0 + (int)blockIdx.y;
+    if (a.active && !as_const(a.active)[item]) return;
+    const int64_t x0 = as_const(xoff)[item], kk = as_const(xoff)[item + 1] - x0;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (parameter, band)
-    if (t >= ktot * F) return;
-    const int64_t g = t / F;
-    const int f = (int)(t - g * F);
-    const int item = find_item(xoff, a.nitems, g);
-    if (a.active && !a.active[item]) return;
-    const int64_t r = g - xoff[item];
-    if (r == 0 && f == 0) a.istatus[item] = 0;
+    if (t == 0) a.istatus[item] = 0;
+    if (t >= kk * F) return;
+    const int64_t r = t / F;
+    const int f = (int)(t - r * F);
     const cptr<ItemDev> it = as_const(a.items) + item;
     const cptr<BandDev> B = as_const(a.band);
-    const double x = a.x[g];
+    const double x = a.x[x0 + r];
     TT *tab = (TT *)a.tables + it->tab_off * (int64_t)F;
     const int64_t k0 = it->k[0], k1 = it->k[1];
     if (r < k0) {
@@ -382,12 +384,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
 }
 
 // ---------------------------------------------------------------------------------------------
-// Segment-shared variant (band weights shared by Q and U).  M = A^T N^-1 A and the adjoint sums
-// G_jk depend only on a pixel's three labels, so they are identical for every pixel of a segment.
-// A pre-pass with one thread per (item, segment) forms M and G in FP64 and the Cholesky factor of
-// M into a 128-byte record; the pixel kernel then streams the data and forms only the
-// data-dependent sums b and h per pixel, reading its segment's record (shared by the segment's
-// lanes through the cache).
+// LDS-staged pixel kernel (band weights shared by Q and U).  Each wavefront first stages, for
+// every segment (constant-label run) of its chunk, the per-band coefficients of its sums in its
+// own LDS slice -- one parallel round of SED-table gathers -- and the band loop then issues only
+// the streaming data loads (a ring of kRing groups prefetched ahead) and reads the coefficients
+// from LDS, whose counter is separate from the vector-memory counter: no table gather ever
+// waits behind a data load.  M = A^T N^-1 A and the adjoint sums G_jk depend only on a pixel's
+// labels; two ways to form them:
+//   per-pixel (SHARED = false): every lane accumulates them over the bands itself;
+//   segment-shared (SHARED = true): while staging, four lanes per segment accumulate them over
+//     interleaved bands and add their partials, and one of them forms the FP64 Cholesky factor
+//     of M into the slice; every pixel then accumulates only its data-dependent sums b and h
+//     (12 FMAs per band) and reads its segment's factor.
+// Chunks with more than kStageSeg segments take the direct-gather per-pixel path.
 // ---------------------------------------------------------------------------------------------
 struct SegRec {  // Cholesky factor of M (inverse diagonal), G_jk, and a positive-definite flag
     double i00, l10, l20, i11, l21, i22;
@@ -395,228 +404,48 @@ struct SegRec {  // Cholesky factor of M (inverse diagonal), G_jk, and a positiv
     double ok;
 };
 
-template <typename TA>
-__device__ __forceinline__ void segment_record(const EvalArgs &a, const int item, const int seg, SegRec *out) {
-    const cptr<BandDev> B = as_const(a.band);
-    const int F = a.nfreq;
-    const cptr<ItemDev> it = as_const(a.items) + item;
-    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
-    const gptr<int> labp = as_global((const int *)L->seg_lab) + 4 * (int64_t)seg;
-    const int64_t kd = it->k[0], kt = it->k[1];
-    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
-    const gptr<TA> pd = tab + (int64_t)labp[0] * F;
-    const gptr<TA> bt = tab + (kd + 2 * (int64_t)labp[1]) * F;
-    const gptr<TA> ss = tab + (kd + 2 * kt + labp[2]) * F;
-    double m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
-    double g01 = 0, g02 = 0, g03 = 0, g11 = 0, g12 = 0, g13 = 0, g21 = 0, g22 = 0, g23 = 0;
-#pragma unroll 2
-    for (int f = 0; f < F; ++f) {
-        const double ad = (double)pd[f] * (double)bt[2 * f];
-        const double dt = (double)bt[2 * f + 1];
-        const double as = (double)ss[f];
-        const double w = B->w[0][f];
-        const double wad = w * ad, was = w * as;
-        m01 += wad;
-        m02 += was;
-        m11 = fma(wad, ad, m11);
-        m12 = fma(wad, as, m12);
-        m22 = fma(was, as, m22);
-        const double c1 = wad * B->ld[f], c2 = wad * dt, c3 = was * B->ls[f];
-        g01 += c1;
-        g02 += c2;
-        g03 += c3;
-        g11 = fma(c1, ad, g11);
-        g12 = fma(c2, ad, g12);
-        g13 = fma(c3, ad, g13);
-        g21 = fma(c1, as, g21);
-        g22 = fma(c2, as, g22);
-        g23 = fma(c3, as, g23);
-    }
-    const double m00 = B->wsum[0];
-    const double l00 = sqrt(m00);
-    const double i00 = 1.0 / l00;
-    const double l10 = m01 * i00, l20 = m02 * i00;
-    const double p1 = m11 - l10 * l10;
-    const double i11 = 1.0 / sqrt(p1);
-    const double l21 = (m12 - l20 * l10) * i11;
-    const double p2 = m22 - l20 * l20 - l21 * l21;
-    const double i22 = 1.0 / sqrt(p2);
-    SegRec r;
-    r.i00 = i00;
-    r.l10 = l10;
-    r.l20 = l20;
-    r.i11 = i11;
-    r.l21 = l21;
-    r.i22 = i22;
-    r.g01 = g01;
-    r.g02 = g02;
-    r.g03 = g03;
-    r.g11 = g11;
-    r.g12 = g12;
-    r.g13 = g13;
-    r.g21 = g21;
-    r.g22 = g22;
-    r.g23 = g23;
-    r.ok = (m00 > 0.0 && p1 > 0.0 && p2 > 0.0) ? 1.0 : 0.0;
-    *out = r;
-}
-
-template <typename TS, typename TA, bool GRAD, int FM>
-__device__ __forceinline__ void unit_seg(const EvalArgs &a, const int item, const int chunk, const int lane,
-                                         const SegRec *recs) {
-    const cptr<BandDev> B = as_const(a.band);
-    const int F = a.nfreq;
-    const cptr<ItemDev> it = as_const(a.items) + item;
-    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
-    const uint64_t head = as_const(L->head)[chunk];
-    const int segbase = as_const(L->seg_base)[chunk];
-    const int nvalid = L->n_incl - chunk * kChunk;
-    const bool valid = lane < nvalid;
-    const int segl = __popcll(head & lanemask_le(lane)) - 1;
-    const gptr<int> labp = as_global((const int *)L->seg_lab) + 4 * (int64_t)(segbase + segl);
-    const int lab_d = labp[0], lab_t = labp[1], lab_s = labp[2];
-    const int64_t kd = it->k[0], kt = it->k[1];
-    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
-    const gptr<TA> pd = tab + (int64_t)lab_d * F;
-    const gptr<TA> bt = tab + (kd + 2 * (int64_t)lab_t) * F;
-    const gptr<TA> ss = tab + (kd + 2 * kt + lab_s) * F;
-    const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
-    const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
-    const gptr<TS> du = dq + (int64_t)F * kChunk;
-
-    SAcc<TA> S[2];
-    S[0] = SAcc<TA>{};
-    S[1] = SAcc<TA>{};
-    auto band = [&](const int f, const TA d0, const TA d1, const TA tpd, const TA tbt, const TA dt, const TA as) {
-        const TA w = Band<TA>::w(B, 0, f);
-        const TA cb1 = w * (tpd * tbt), cb2 = w * as;
-        const TA ch1 = cb1 * Band<TA>::ld(B, f), ch2 = cb1 * dt, ch3 = cb2 * Band<TA>::ls(B, f);
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const TA dv = s ? d1 : d0;
-            SAcc<TA> &c = S[s];
-            c.b0 = fma(w, dv, c.b0);
-            c.b1 = fma(cb1, dv, c.b1);
-            c.b2 = fma(cb2, dv, c.b2);
-            if (GRAD) {
-                c.h1 = fma(ch1, dv, c.h1);
-                c.h2 = fma(ch2, dv, c.h2);
-                c.h3 = fma(ch3, dv, c.h3);
-            }
-        }
-    };
-    band_loop<FM, CS_BAND_GROUP, TS, TA>(F, dq, du, pd, bt, ss, band);
-
-    // the segment's record (16 doubles, the same address for every lane of the segment)
-    const gptr<double> rp = as_global((const double *)recs) + 16 * (int64_t)segl;
-    SegRec R;
-    R.i00 = rp[0];
-    R.l10 = rp[1];
-    R.l20 = rp[2];
-    R.i11 = rp[3];
-    R.l21 = rp[4];
-    R.i22 = rp[5];
-    R.g01 = rp[6];
-    R.g02 = rp[7];
-    R.g03 = rp[8];
-    R.g11 = rp[9];
-    R.g12 = rp[10];
-    R.g13 = rp[11];
-    R.g21 = rp[12];
-    R.g22 = rp[13];
-    R.g23 = rp[14];
-    R.ok = rp[15];
-    const bool ok = R.ok != 0.0;
-    double fpix = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const SAcc<TA> &q = S[s];
-        const double z0 = (double)q.b0 * R.i00;
-        const double z1 = ((double)q.b1 - R.l10 * z0) * R.i11;
-        const double z2 = ((double)q.b2 - R.l20 * z0 - R.l21 * z1) * R.i22;
-        fpix -= z0 * z0 + z1 * z1 + z2 * z2;
-        if (GRAD) {
-            const double s2 = z2 * R.i22;
-            const double s1 = (z1 - R.l21 * s2) * R.i11;
-            const double s0 = (z0 - R.l10 * s1 - R.l20 * s2) * R.i00;
-            const double e1 = (double)q.h1 - (s0 * R.g01 + s1 * R.g11 + s2 * R.g21);
-            const double e2 = (double)q.h2 - (s0 * R.g02 + s1 * R.g12 + s2 * R.g22);
-            const double e3 = (double)q.h3 - (s0 * R.g03 + s1 * R.g13 + s2 * R.g23);
-            g1 -= 2.0 * s1 * e1;
-            g2 -= 2.0 * s1 * e2;
-            g3 -= 2.0 * s2 * e3;
-        }
-    }
-    if (!valid) {
-        fpix = 0.0;
-        g1 = g2 = g3 = 0.0;
-    } else if (!ok) {
-        fpix = g1 = g2 = g3 = __builtin_nan("");
-    }
-    const uint64_t bad = __ballot(valid && !ok);
-    if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
-    seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (it->part_off + segbase + segl) * 4);
-}
-
-// Pre-pass: one thread per (item, segment) writes the segment's record.
-template <typename TA>
-__global__ __launch_bounds__(256) void k_seg_records(const EvalArgs a, const int64_t *segoff) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= segoff[a.nitems]) return;
-    const int item = find_item(segoff, a.nitems, g);
-    if (a.active && !a.active[item]) return;
-    const int seg = (int)(g - segoff[item]);
-    SegRec *out = (SegRec *)a.records + (as_const(a.items) + item)->part_off + seg;
-    segment_record<TA>(a, item, seg, out);
-}
-
-template <typename TS, typename TA, bool GRAD, int FM>
-__global__ __launch_bounds__(512) void k_pixel_seg(const EvalArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = a.waves_per_block;
-    const int64_t nb = gridDim.x;
-    const int64_t lb = logical_block(a.xcd_remap);
-    const cptr<int> units = as_const((const int *)a.units);
-    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
-        const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
-        const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
-        if (a.active && !as_const(a.active)[item]) continue;
-        const cptr<ItemDev> it = as_const(a.items) + item;
-        const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
-        const int segbase = as_const(L->seg_base)[chunk];
-        unit_seg<TS, TA, GRAD, FM>(a, item, chunk, lane, (const SegRec *)a.records + it->part_off + segbase);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// LDS-staged pixel kernel (band weights shared by Q and U).  Each wavefront first stages, for
-// every segment of its chunk, the mixing-matrix columns (a_d, da_d/dT / a_d, a_s) of every band
-// into its own LDS slice -- one parallel round of SED-table gathers -- and, in the segment-shared
-// mode, the segments' records.  The band loop then issues only the streaming data loads (a ring
-// of kRing groups prefetched ahead) and reads the columns from LDS, whose counter is separate
-// from the vector-memory counter: no table gather ever waits behind a data load.  Chunks with
-// more than kStageSeg segments use the direct-gather path.
-// ---------------------------------------------------------------------------------------------
-template <typename TA>
-struct StageCfg;
-template <>
-struct StageCfg<float> {
-    static constexpr int kSeg = 16;
-};
-template <>
-struct StageCfg<double> {
-    static constexpr int kSeg = 10;
-};
+constexpr int kStageSeg = 12;  // segments staged per chunk (more: direct-gather path)
+constexpr int kLanesPerSeg = 4;
 
 template <typename TA>
 struct alignas(4 * sizeof(TA)) Col4 {
-    TA ad, dt, as, pad;
+    TA x, y, z, w;
 };
 
+// LDS slice of one wavefront: Col4 [kStageSeg][F]; the segment-shared mode adds TA [kStageSeg][F]
+// (16-byte padded) and SegRec [kStageSeg]
 template <typename TA>
+__host__ __device__ constexpr size_t stage_col_bytes(int F) {
+    return (size_t)kStageSeg * (size_t)F * sizeof(Col4<TA>);
+}
+template <typename TA>
+__host__ __device__ constexpr size_t stage_c5_bytes(int F) {
+    return ((size_t)kStageSeg * (size_t)F * sizeof(TA) + 15) & ~(size_t)15;
+}
+template <typename TA, bool SHARED>
 __host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
-    return (size_t)StageCfg<TA>::kSeg * (size_t)F * sizeof(Col4<TA>) + (size_t)StageCfg<TA>::kSeg * sizeof(SegRec);
+    return SHARED ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kStageSeg * sizeof(SegRec)
+                  : stage_col_bytes<TA>(F);
+}
+
+// Sum over the four lanes of a quad, the same value in each: (v0 + v1) + (v2 + v3) via DPP
+// quad permutations (every lane of the wavefront must be active).
+template <int kCtrl>
+__device__ __forceinline__ float quad_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ double quad_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ T quad_sum(T v) {
+    v = v + quad_swap<0xB1>(v);  // lanes (1,0,3,2)
+    v = v + quad_swap<0x4E>(v);  // lanes (2,3,0,1)
+    return v;
 }
 
 template <typename TS, typename TA, bool GRAD, bool SHARED>
@@ -651,30 +480,150 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             ru[r][j] = du[f * kChunk];
         }
 
-    // stage the columns of the chunk's segments (and their records)
     Col4<TA> *cols = (Col4<TA> *)wave_lds;
-    SegRec *recs = (SegRec *)(wave_lds + (size_t)StageCfg<TA>::kSeg * F * sizeof(Col4<TA>));
+    TA *c5 = (TA *)(wave_lds + stage_col_bytes<TA>(F));
+    SegRec *recs = (SegRec *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
     const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
     const gptr<int> seglab = as_global((const int *)L->seg_lab) + 4 * (int64_t)segbase;
-    for (int e = lane; e < nseg * F; e += kChunk) {
-        const int sg = e / F, f = e - sg * F;
-        const int ld = seglab[4 * sg], lt = seglab[4 * sg + 1], ls = seglab[4 * sg + 2];
-        const TA pdv = tab[(int64_t)ld * F + f];
-        const TA btv = tab[(kd + 2 * (int64_t)lt) * F + 2 * f];
-        const TA dtv = tab[(kd + 2 * (int64_t)lt) * F + 2 * f + 1];
-        const TA ssv = tab[(kd + 2 * kt + ls) * F + f];
-        Col4<TA> c;
-        c.ad = pdv * btv;
-        c.dt = dtv;
-        c.as = ssv;
-        c.pad = (TA)0;
-        cols[e] = c;
-    }
-    if (SHARED && lane < nseg) {
-        const gptr<double> src = as_global((const double *)a.records) + 16 * (it->part_off + segbase + lane);
-        double *dst = (double *)(recs + lane);
+    if (!SHARED) {
+        // columns (a_d, da_d/dT / a_d, a_s) of every (segment, band), in phases of kPh rounds of
+        // the wavefront whose gathers are all issued before their first use
+        constexpr int kPh = sizeof(TA) == 4 ? 6 : 3;  // measured best on gfx950 at F = 22
+        const int ne = nseg * F;
+        for (int e0 = 0; e0 < ne; e0 += kPh * kChunk) {
+            int sgi[kPh], fi[kPh];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) dst[k] = src[k];
+            for (int i = 0; i < kPh; ++i) {
+                const int e = e0 + lane + i * kChunk;
+                const int ec = e < ne ? e : ne - 1;
+                sgi[i] = ec / F;
+                fi[i] = ec - sgi[i] * F;
+            }
+            int lab[kPh][3];
+#pragma unroll
+            for (int i = 0; i < kPh; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) lab[i][j] = seglab[4 * sgi[i] + j];
+            TA pdv[kPh], btv[kPh], dtv[kPh], ssv[kPh];
+#pragma unroll
+            for (int i = 0; i < kPh; ++i) {
+                const int f = fi[i];
+                pdv[i] = tab[(int64_t)lab[i][0] * F + f];
+                btv[i] = tab[(kd + 2 * (int64_t)lab[i][1]) * F + 2 * f];
+                dtv[i] = tab[(kd + 2 * (int64_t)lab[i][1]) * F + 2 * f + 1];
+                ssv[i] = tab[(kd + 2 * kt + lab[i][2]) * F + f];
+            }
+#pragma unroll
+            for (int i = 0; i < kPh; ++i) {
+                const int e = e0 + lane + i * kChunk;
+                if (e < ne) cols[e] = Col4<TA>{pdv[i] * btv[i], dtv[i], ssv[i], (TA)0};
+            }
+        }
+    } else {
+        // coefficients (w a_d, w a_s, w a_d ln(nu/nu0d), w da_d/dT, w a_s ln(nu/nu0s)) of every
+        // (segment, band), and the segment's M and G sums: lane = 4 segment + part, bands
+        // part, part + 4, ...; every gather is issued before the first use
+        // phases of kPh bands per lane, every gather of a phase issued before its first use
+        constexpr int kPh = sizeof(TA) == 4 ? 4 : 2;
+        const int sg = lane / kLanesPerSeg, part = lane % kLanesPerSeg;
+        const bool act = sg < nseg;
+        const int sgc = act ? sg : 0;
+        const int ld = seglab[4 * sgc], lt = seglab[4 * sgc + 1], ls = seglab[4 * sgc + 2];
+        const gptr<TA> pd = tab + (int64_t)ld * F;
+        const gptr<TA> bt = tab + (kd + 2 * (int64_t)lt) * F;
+        const gptr<TA> ss = tab + (kd + 2 * kt + ls) * F;
+        const gptr<BandDev> Bg = as_global((const BandDev *)a.band);
+        WAcc<TA> P = WAcc<TA>{};
+        for (int f0 = 0; f0 < F; f0 += kLanesPerSeg * kPh) {
+            TA pdv[kPh], btv[kPh], dtv[kPh], ssv[kPh], wv[kPh], ldv[kPh], lsv[kPh];
+#pragma unroll
+            for (int i = 0; i < kPh; ++i) {
+                const int fr = f0 + part + kLanesPerSeg * i;
+                const int f = fr < F ? fr : F - 1;
+                if constexpr (sizeof(TA) == 8) {
+                    wv[i] = Bg->w[0][f];
+                    ldv[i] = Bg->ld[f];
+                    lsv[i] = Bg->ls[f];
+                } else {
+                    wv[i] = Bg->wf[0][f];
+                    ldv[i] = Bg->ldf[f];
+                    lsv[i] = Bg->lsf[f];
+                }
+                pdv[i] = pd[f];
+                btv[i] = bt[2 * f];
+                dtv[i] = bt[2 * f + 1];
+                ssv[i] = ss[f];
+            }
+#pragma unroll
+            for (int i = 0; i < kPh; ++i) {
+                const int f = f0 + part + kLanesPerSeg * i;
+                const bool use = act && f < F;
+                const TA ad = pdv[i] * btv[i], dt = dtv[i], as = ssv[i];
+                const TA w = use ? wv[i] : (TA)0;  // nothing past F or past the chunk's segments
+                const TA cad = w * ad, cas = w * as;
+                const TA c1 = cad * ldv[i], c2 = cad * dt, c3 = cas * lsv[i];
+                if (use) {
+                    cols[sg * F + f] = Col4<TA>{cad, cas, c1, c2};
+                    c5[sg * F + f] = c3;
+                }
+                P.m01 += cad;
+                P.m02 += cas;
+                P.m11 = fma(cad, ad, P.m11);
+                P.m12 = fma(cad, as, P.m12);
+                P.m22 = fma(cas, as, P.m22);
+                if (GRAD) {
+                    P.g01 += c1;
+                    P.g02 += c2;
+                    P.g03 += c3;
+                    P.g11 = fma(c1, ad, P.g11);
+                    P.g12 = fma(c2, ad, P.g12);
+                    P.g13 = fma(c3, ad, P.g13);
+                    P.g21 = fma(c1, as, P.g21);
+                    P.g22 = fma(c2, as, P.g22);
+                    P.g23 = fma(c3, as, P.g23);
+                }
+            }
+        }
+        P.m01 = quad_sum(P.m01);
+        P.m02 = quad_sum(P.m02);
+        P.m11 = quad_sum(P.m11);
+        P.m12 = quad_sum(P.m12);
+        P.m22 = quad_sum(P.m22);
+        if (GRAD) {
+            P.g01 = quad_sum(P.g01);
+            P.g02 = quad_sum(P.g02);
+            P.g03 = quad_sum(P.g03);
+            P.g11 = quad_sum(P.g11);
+            P.g12 = quad_sum(P.g12);
+            P.g13 = quad_sum(P.g13);
+            P.g21 = quad_sum(P.g21);
+            P.g22 = quad_sum(P.g22);
+            P.g23 = quad_sum(P.g23);
+        }
+        if (part == 0 && sg < nseg) {
+            const double m00 = (double)Band<TA>::wsum(B, 0);
+            const double m01 = P.m01, m02 = P.m02, m11 = P.m11, m12 = P.m12, m22 = P.m22;
+            SegRec r;
+            r.i00 = 1.0 / sqrt(m00);
+            r.l10 = m01 * r.i00;
+            r.l20 = m02 * r.i00;
+            const double p1 = m11 - r.l10 * r.l10;
+            r.i11 = 1.0 / sqrt(p1);
+            r.l21 = (m12 - r.l20 * r.l10) * r.i11;
+            const double p2 = m22 - r.l20 * r.l20 - r.l21 * r.l21;
+            r.i22 = 1.0 / sqrt(p2);
+            r.ok = ((m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0)) ? 1.0 : 0.0;
+            r.g01 = P.g01;
+            r.g02 = P.g02;
+            r.g03 = P.g03;
+            r.g11 = P.g11;
+            r.g12 = P.g12;
+            r.g13 = P.g13;
+            r.g21 = P.g21;
+            r.g22 = P.g22;
+            r.g23 = P.g23;
+            recs[sg] = r;
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -685,29 +634,46 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     S[0] = SAcc<TA>{};
     S[1] = SAcc<TA>{};
     const Col4<TA> *mycols = cols + segl * F;
+    const TA *myc5 = c5 + segl * F;
     auto band = [&](const int f, const TA d0, const TA d1) {
         const Col4<TA> c = mycols[f];
         const TA w = Band<TA>::w(B, 0, f);
-        const TA lgd = Band<TA>::ld(B, f), lgs = Band<TA>::ls(B, f);
-        const TA wad = w * c.ad, was = w * c.as;
-        const TA c1 = wad * lgd, c2 = wad * c.dt, c3 = was * lgs;
-        if (!SHARED) {
-            A.m01 += wad;
-            A.m02 += was;
-            A.m11 = fma(wad, c.ad, A.m11);
-            A.m12 = fma(wad, c.as, A.m12);
-            A.m22 = fma(was, c.as, A.m22);
-            if (GRAD) {
-                A.g01 += c1;
-                A.g02 += c2;
-                A.g03 += c3;
-                A.g11 = fma(c1, c.ad, A.g11);
-                A.g12 = fma(c2, c.ad, A.g12);
-                A.g13 = fma(c3, c.ad, A.g13);
-                A.g21 = fma(c1, c.as, A.g21);
-                A.g22 = fma(c2, c.as, A.g22);
-                A.g23 = fma(c3, c.as, A.g23);
+        if (SHARED) {
+            const TA c3 = myc5[f];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const TA dv = s ? d1 : d0;
+                SAcc<TA> &q = S[s];
+                q.b0 = fma(w, dv, q.b0);
+                q.b1 = fma(c.x, dv, q.b1);
+                q.b2 = fma(c.y, dv, q.b2);
+                if (GRAD) {
+                    q.h1 = fma(c.z, dv, q.h1);
+                    q.h2 = fma(c.w, dv, q.h2);
+                    q.h3 = fma(c3, dv, q.h3);
+                }
             }
+            return;
+        }
+        const TA ad = c.x, dt = c.y, as = c.z;
+        const TA lgd = Band<TA>::ld(B, f), lgs = Band<TA>::ls(B, f);
+        const TA wad = w * ad, was = w * as;
+        const TA c1 = wad * lgd, c2 = wad * dt, c3 = was * lgs;
+        A.m01 += wad;
+        A.m02 += was;
+        A.m11 = fma(wad, ad, A.m11);
+        A.m12 = fma(wad, as, A.m12);
+        A.m22 = fma(was, as, A.m22);
+        if (GRAD) {
+            A.g01 += c1;
+            A.g02 += c2;
+            A.g03 += c3;
+            A.g11 = fma(c1, ad, A.g11);
+            A.g12 = fma(c2, ad, A.g12);
+            A.g13 = fma(c3, ad, A.g13);
+            A.g21 = fma(c1, as, A.g21);
+            A.g22 = fma(c2, as, A.g22);
+            A.g23 = fma(c3, as, A.g23);
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -743,7 +709,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         }
     }
 
-    // a5/a6: Cholesky factor (per pixel, or the staged segment record), then F and gradient
+    // a5/a6: Cholesky factor (per pixel, or the segment's from the slice), then F and gradient
     double i00, l10, l20, i11, l21, i22, G[9];
     bool ok;
     if (SHARED) {
@@ -817,37 +783,34 @@ __global__ __launch_bounds__(512) void k_pixel_stage(const EvalArgs a) {
     const int64_t nb = gridDim.x;
     const int64_t lb = logical_block(a.xcd_remap);
     const cptr<int> units = as_const((const int *)a.units);
-    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA>(a.nfreq);
+    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA, SHARED>(a.nfreq);
     for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
         const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
         const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
         if (a.active && !as_const(a.active)[item]) continue;
         const cptr<LayoutDev> L = as_const(a.layouts) + (as_const(a.items) + item)->layout;
         const int nseg = as_const(L->seg_base)[chunk + 1] - as_const(L->seg_base)[chunk];
-        if (nseg <= StageCfg<TA>::kSeg) {
+        if (nseg <= kStageSeg)
             unit_staged<TS, TA, GRAD, SHARED>(a, item, chunk, lane, wave_lds);
-        } else if (SHARED) {
-            const int segbase = as_const(L->seg_base)[chunk];
-            unit_seg<TS, TA, GRAD, 0>(a, item, chunk, lane,
-                                      (const SegRec *)a.records + (as_const(a.items) + item)->part_off + segbase);
-        } else {
+        else
             unit_pixel<TS, TA, GRAD, 0, 0>(a, item, chunk, lane);
-        }
     }
 }
 
 // ---------------------------------------------------------------------------------------------
 // a7 (second level): deterministic compensated sums over each cluster's segments
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int64_t ktot, double *grad,
+// Grid as for k_sed: x over an item's clusters, y over items.
+__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, double *grad,
                                                   double *cluster_f) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ktot) return;
-    const int item = find_item(xoff, a.nitems, g);
-    if (a.active && !a.active[item]) return;
+    const int item = item0 + (int)blockIdx.y;
+    if (a.active && !as_const(a.active)[item]) return;
+    const int64_t x0 = as_const(xoff)[item];
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= as_const(xoff)[item + 1] - x0) return;
+    const int64_t g = x0 + r;
     const ItemDev &it = a.items[item];
     const LayoutDev &L = a.layouts[it.layout];
-    int64_t r = g - xoff[item];
     int j = 0;
     if (r >= it.k[0]) {
         r -= it.k[0];
@@ -936,41 +899,33 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_f(const EvalArgs a, double 
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
-template <typename TS, typename TA, bool GRAD, int FM>
-static void launch_pixel_f(int wm, bool shared, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    // LDS staging needs stage_bytes_per_wave per wavefront; a workgroup may hold at most 64 KiB
-    const size_t lds = stage_bytes_per_wave<TA>(a.nfreq) * (block.x / kChunk);
-    const bool staged = lds <= 65536;
-    if (wm == 0 && shared && staged)
+// wm == 0 (band weights shared by Q and U): the LDS-staged kernel, lds bytes per workgroup;
+// otherwise the direct-gather kernel with separate Q/U (wm = 1) or per-pixel (wm = 2) weights.
+template <typename TS, typename TA, bool GRAD>
+static void launch_pixel_t(int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (wm == 0 && shared)
         hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, true>), grid, block, lds, s, a);
-    else if (wm == 0 && staged)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, false>), grid, block, lds, s, a);
-    else if (wm == 0 && shared)
-        hipLaunchKernelGGL((k_pixel_seg<TS, TA, GRAD, FM>), grid, block, 0, s, a);
     else if (wm == 0)
-        hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 0, FM>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, false>), grid, block, lds, s, a);
     else if (wm == 1)
         hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, 0>), grid, block, 0, s, a);
     else
         hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 2, 0>), grid, block, 0, s, a);
 }
 
-// The compile-time band-count instantiation (FM > 0, whole data column requested up front) needs
-// more registers than it saves in latency on gfx950 (measured: slower for every precision at
-// F = 22); every band count runs the grouped runtime-F loop.
-template <typename TS, typename TA, bool GRAD>
-static void launch_pixel_t(int wm, bool shared, int F, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    (void)F;
-    launch_pixel_f<TS, TA, GRAD, 0>(wm, shared, grid, block, s, a);
-}
-
 template <typename TS, typename TA>
-static void launch_pixel_g(bool grad, int wm, bool shared, int F, dim3 grid, dim3 block, hipStream_t s,
+static void launch_pixel_g(bool grad, int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s,
                            const EvalArgs &a) {
     if (grad)
-        launch_pixel_t<TS, TA, true>(wm, shared, F, grid, block, s, a);
+        launch_pixel_t<TS, TA, true>(wm, shared, lds, grid, block, s, a);
     else
-        launch_pixel_t<TS, TA, false>(wm, shared, F, grid, block, s, a);
+        launch_pixel_t<TS, TA, false>(wm, shared, lds, grid, block, s, a);
+}
+
+// LDS slice of one wavefront of the staged kernel in an arithmetic mode
+static size_t stage_bytes(cs_precision mode, bool shared, int F) {
+    if (mode == CS_FP32_BULK) return shared ? stage_bytes_per_wave<float, true>(F) : stage_bytes_per_wave<float, false>(F);
+    return shared ? stage_bytes_per_wave<double, true>(F) : stage_bytes_per_wave<double, false>(F);
 }
 
 EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active) {
@@ -985,7 +940,6 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
     a.tables = p->wsp + w.tables;
     a.band = (const BandDev *)(p->wsp + w.band);
     a.partials = (double *)(p->wsp + w.partials);
-    a.records = p->wsp + w.records;
     a.istatus = (int32_t *)(p->wsp + w.istatus);
     a.active = active;
     a.x = x;
@@ -997,36 +951,43 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
 }
 
 cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s) {
-    const int64_t ktot = p->xoff[p->B];
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)p->B);
-    const unsigned sblocks = (unsigned)((ktot * p->F + 255) / 256);
-    if (fp32_tables)
-        hipLaunchKernelGGL(k_sed<float>, dim3(sblocks), dim3(256), 0, s, a, xoff_dev, ktot);
-    else
-        hipLaunchKernelGGL(k_sed<double>, dim3(sblocks), dim3(256), 0, s, a, xoff_dev, ktot);
-    CSI_HIP(hipGetLastError());
+    const unsigned sblocks = (unsigned)((p->kmax_item * p->F + 255) / 256);
+    for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
+        const dim3 grid(sblocks, (unsigned)std::min(kMaxGridY, p->B - b0));
+        if (fp32_tables)
+            hipLaunchKernelGGL(k_sed<float>, grid, dim3(256), 0, s, a, xoff_dev, b0);
+        else
+            hipLaunchKernelGGL(k_sed<double>, grid, dim3(256), 0, s, a, xoff_dev, b0);
+        CSI_HIP(hipGetLastError());
+    }
     return CS_OK;
 }
 
 cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl, double *grad,
                       double *cluster_f, int32_t *status, bool want_grad, cs_precision mode, hipStream_t s) {
     const WsLayout &w = p->ws;
-    const EvalArgs a = make_eval_args(p, x, active);
-    const int64_t ktot = p->xoff[p->B];
+    EvalArgs a = make_eval_args(p, x, active);
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
     const bool t32 = (mode == CS_FP32_BULK);
-    const unsigned kblocks = (unsigned)((ktot + 255) / 256);
+    const unsigned kblocks = (unsigned)((p->kmax_item + 255) / 256);
 
     const cs_status sst = launch_sed(p, a, t32, s);
     if (sst != CS_OK) return sst;
 
-    const int wpb = p->sched.waves_per_block;
+    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
+    const bool shared = p->sched.shared_segments != 0;
+    // the staged kernel's workgroup holds at most 64 KiB of LDS: fewer wavefronts per workgroup
+    // when the slices do not fit (same arithmetic, work only regrouped)
+    int wpb = p->sched.waves_per_block;
+    const size_t per_wave = wm == 0 ? stage_bytes(mode, shared, p->F) : 0;
+    while (wpb > 1 && per_wave * (size_t)wpb > 65536) wpb >>= 1;
+    a.waves_per_block = wpb;
     int64_t nblocks = (p->nunits + wpb - 1) / wpb;
     if (p->sched.blocks_per_cu > 0) nblocks = std::min<int64_t>(nblocks, (int64_t)p->sched.blocks_per_cu * kNumCu);
     if (nblocks < 1) nblocks = 1;
     const dim3 grid((unsigned)nblocks), block((unsigned)(64 * wpb));
-    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
-    const bool shared = p->sched.shared_segments != 0;
+    const size_t lds = per_wave * (size_t)wpb;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (p->timing) {
         if (p->events_used == p->events.size()) {
@@ -1040,32 +1001,21 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
         ++p->events_used;
         CSI_HIP(hipEventRecord(e0, s));
     }
-    if (wm == 0 && shared) {
-        const int64_t nsegs = p->segoff[p->B];
-        const int64_t *segoff_dev = (const int64_t *)(p->wsp + w.segoff);
-        if (nsegs > 0) {
-            if (t32)
-                hipLaunchKernelGGL(k_seg_records<float>, dim3((unsigned)((nsegs + 255) / 256)), dim3(256), 0, s, a,
-                                   segoff_dev);
-            else
-                hipLaunchKernelGGL(k_seg_records<double>, dim3((unsigned)((nsegs + 255) / 256)), dim3(256), 0, s, a,
-                                   segoff_dev);
-            CSI_HIP(hipGetLastError());
-        }
-    }
     if (mode == CS_FP64)
-        launch_pixel_g<double, double>(want_grad, wm, shared, p->F, grid, block, s, a);
+        launch_pixel_g<double, double>(want_grad, wm, shared, lds, grid, block, s, a);
     else if (mode == CS_FP32_BULK)
-        launch_pixel_g<float, float>(want_grad, wm, shared, p->F, grid, block, s, a);
+        launch_pixel_g<float, float>(want_grad, wm, shared, lds, grid, block, s, a);
     else
-        launch_pixel_g<float, double>(want_grad, wm, shared, p->F, grid, block, s, a);
+        launch_pixel_g<float, double>(want_grad, wm, shared, lds, grid, block, s, a);
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 
     if (want_grad || cluster_f) {
-        hipLaunchKernelGGL(k_fin_grad, dim3(kblocks), dim3(256), 0, s, a, xoff_dev, ktot, want_grad ? grad : nullptr,
-                           cluster_f);
-        CSI_HIP(hipGetLastError());
+        for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
+            hipLaunchKernelGGL(k_fin_grad, dim3(kblocks, (unsigned)std::min(kMaxGridY, p->B - b0)), dim3(256), 0, s, a,
+                               xoff_dev, b0, want_grad ? grad : nullptr, cluster_f);
+            CSI_HIP(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(k_fin_f, dim3(p->B), dim3(kFinThreads), 0, s, a, neg2logl, status);
     CSI_HIP(hipGetLastError());

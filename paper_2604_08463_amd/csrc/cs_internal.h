@@ -16,6 +16,7 @@ constexpr int kChunk = 64;  // pixels per work unit = lanes of one wavefront
 constexpr int kFMax = 32;   // largest supported band count (register tile)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int kNumCu = 256;
+constexpr int kMaxGridY = 65535;  // largest grid dimension y
 
 // Per-band constants, computed on the host in FP64 and stored once in the workspace.
 struct BandDev {
@@ -70,7 +71,6 @@ struct EvalArgs {
     void *tables;        // per item: PD [K_d][F], BTDT [K_T][F][2], SS [K_s][F]
     const BandDev *band;
     double *partials;    // [segment][4]: f, dF/dbeta_d, dF/dT_d, dF/dbeta_s
-    void *records;       // [segment] 128-byte records of the segment-shared path
     int32_t *istatus;    // [B] status bits of the current evaluation
     const int32_t *active;  // nullable [B]: 0 = skip item (converged optimiser items)
     const double *x;     // packed parameters
@@ -83,7 +83,7 @@ struct EvalArgs {
 // Workspace regions (byte offsets, 256-aligned), see carve_workspace().
 struct WsLayout {
     size_t band, items, layouts, units, keys, order, head, seg_base, seg_lab, seg_perm, seg_off,
-        counts, dpack, wpack, tables, partials, records, segoff, istatus, total;
+        counts, dpack, wpack, tables, partials, segoff, istatus, total;
     size_t keys_stride, p64, nchunk_max, np2, kmax[3];
 };
 
@@ -110,6 +110,7 @@ struct cs_problem {
     int32_t L = 1;          // number of label layouts
     int key_bits[4] = {0, 0, 0, 0};
     std::vector<int64_t> xoff;     // [B+1]
+    int64_t kmax_item = 1;         // largest parameter count of one item
     std::vector<int64_t> taboff;   // [B+1] table rows
     std::vector<int64_t> segoff;   // [B+1] segments of the items (after prepare)
     csi::WsLayout ws;

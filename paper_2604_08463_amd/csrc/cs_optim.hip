@@ -345,6 +345,282 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
     }
 }
 
+// The same step with the item's vectors held in registers: thread t owns elements k NT + t,
+// k < PT (K <= NT PT), so every load instruction of a wavefront is one contiguous span.  y, g,
+// the free mask and the direction stay in registers for the whole step, each two-loop pass
+// streams only its pair (s_j, t_j) and keeps the vector the next pass's pending update needs,
+// and every sum is formed in the same order as in k_opt_update.
+template <int NT, int PT>
+__global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
+    const int item = blockIdx.x;
+    if (!a.active[item]) return;
+    __shared__ double red[8][16];
+    __shared__ double rho[32], alp[32];
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    const int tid = threadIdx.x;
+    const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
+    double *yg = a.y + o, *gg = a.g + o, *pgl = a.p + o, *ytg = a.yt + o, *xtg = a.xt + o;
+    OptItem s = a.st[item];  // every thread holds the same copy
+    s.nevals += 1;
+    const double fe = a.fe[item];
+    const int32_t est = a.estat[item];
+    const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
+    int32_t finish = 0;
+    bool need_dir = false;
+
+    // y, g and the direction (which also holds the two-loop vector) of the thread's elements
+    double y[PT], g[PT], pv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t i = (int64_t)k * NT + tid;
+        const bool in = i < K;
+        y[k] = in ? yg[i] : 0.0;
+        g[k] = in ? gg[i] : 0.0;
+        pv[k] = in ? pgl[i] : 0.0;
+    }
+
+    if (s.state == ST_INIT || s.state == ST_REINIT) {
+        if (!evalok) {
+            finish = est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE);
+            if (!finish) finish = CS_ITEM_NONFINITE;
+        } else {
+            double v[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                if (i < K) {
+                    g[k] = ge[i] * (hi[i] - lo[i]);
+                    if (is_free(y[k], g[k])) v[0] += g[k] * g[k];
+                }
+            }
+            block_sum<1, NT>(v, red);
+            s.f = fe;
+            if (s.state == ST_INIT) {
+                s.pg0 = sqrt(v[0]);
+                if (!isfinite(s.pg0))
+                    finish = CS_ITEM_NONFINITE;
+                else if (s.pg0 == 0.0)
+                    finish = CS_ITEM_CONVERGED;
+            }
+            if (!finish && s.iter >= a.max_iter) finish = CS_ITEM_MAXITER;
+            need_dir = !finish;
+        }
+    } else if (s.state == ST_SEARCH) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (evalok) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                if (i < K) {
+                    const double si = ytg[i] - y[k], gti = ge[i] * (hi[i] - lo[i]), ti = gti - g[k];
+                    v[0] += si * ti;
+                    v[1] += si * si;
+                    v[2] += ti * ti;
+                    v[3] += gti * si;
+                }
+            }
+        }
+        block_sum<4, NT>(v, red);
+        const bool flat = fabs(fe - s.f) <= kFlatRel * fabs(s.f) && v[3] <= 0.0;
+        if (evalok && v[1] > 0.0 && (fe <= s.f + a.c1 * s.dec || flat)) {  // never accept a null step
+            const bool keep = v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2]);
+            const int nw = keep ? (s.newest + 1) % a.m : s.newest;
+            double *Sn = a.S + (int64_t)nw * a.ktot + o, *Tn = a.T + (int64_t)nw * a.ktot + o;
+            double pg[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                if (i < K) {
+                    const double yti = ytg[i], gti = ge[i] * (hi[i] - lo[i]);
+                    if (keep) {
+                        Sn[i] = yti - y[k];
+                        Tn[i] = gti - g[k];
+                    }
+                    y[k] = yti;
+                    g[k] = gti;
+                    if (is_free(y[k], g[k])) pg[0] += g[k] * g[k];
+                }
+            }
+            block_sum<1, NT>(pg, red);
+            if (keep) {
+                s.newest = nw;
+                if (s.npairs < a.m) s.npairs += 1;
+            }
+            s.f = fe;
+            s.iter += 1;
+            if (sqrt(pg[0]) <= a.gtol * s.pg0)
+                finish = CS_ITEM_CONVERGED;
+            else if (s.iter >= a.max_iter)
+                finish = CS_ITEM_MAXITER;
+            need_dir = !finish;
+        } else {
+            s.nbt += 1;
+            if (s.nbt > a.max_backtracks)
+                finish = CS_ITEM_LS_FAIL;
+            else
+                s.alpha *= 0.5;
+        }
+    }
+
+    if (need_dir) {
+        // two-loop recursion on the free set, q (in pv) = P g; carry = t (backward) or s (forward)
+        // of the last used pair, whose update is applied at the start of the next pass
+        unsigned fr = 0;
+        double carry[PT];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const bool f = ((int64_t)k * NT + tid < K) && is_free(y[k], g[k]);
+            fr |= (unsigned)f << k;
+            pv[k] = f ? g[k] : 0.0;
+            carry[k] = 0.0;
+        }
+        const int np = s.npairs, m = a.m;
+        double gamma = 1.0;
+        bool gamma_set = false;
+        int used = 0;
+        bool pend = false;
+        double penda = 0.0;
+        for (int c = 0; c < np; ++c) {
+            const int j = ((s.newest - c) % m + m) % m;
+            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                const bool f = (fr >> k) & 1u;
+                if (pend && f) pv[k] -= penda * carry[k];
+                double ti = 0.0;
+                if (f) {
+                    const double si = Sj[i];
+                    ti = Tj[i];
+                    v[0] += si * ti;
+                    v[1] += si * si;
+                    v[2] += ti * ti;
+                    v[3] += si * pv[k];
+                }
+                carry[k] = ti;
+            }
+            block_sum<4, NT>(v, red);
+            if (!(v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2])) || v[2] == 0.0) {
+                if (tid == 0) rho[j] = 0.0;
+                pend = false;
+                continue;
+            }
+            const double rj = 1.0 / v[0];
+            if (!gamma_set) {
+                gamma = v[0] / v[2];
+                gamma_set = true;
+            }
+            const double aj = rj * v[3];
+            if (tid == 0) {
+                rho[j] = rj;
+                alp[j] = aj;
+            }
+            pend = true;
+            penda = aj;
+            ++used;
+        }
+        __syncthreads();  // rho / alp visible to every thread
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            if (pend && ((fr >> k) & 1u)) pv[k] -= penda * carry[k];
+            pv[k] *= gamma;
+        }
+        bool spend = false;
+        double pendc = 0.0;
+        for (int c = np - 1; c >= 0; --c) {
+            const int j = ((s.newest - c) % m + m) % m;
+            const double rj = rho[j];
+            if (rj == 0.0) continue;
+            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+            double v[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                const bool f = (fr >> k) & 1u;
+                if (spend && f) pv[k] += carry[k] * pendc;
+                double si = 0.0;
+                if (f) {
+                    si = Sj[i];
+                    v[0] += Tj[i] * pv[k];
+                }
+                carry[k] = si;
+            }
+            block_sum<1, NT>(v, red);
+            spend = true;
+            pendc = alp[j] - rj * v[0];
+        }
+        // p = -(H P g) on the free set, p.g, max |p|
+        double v[2] = {0.0, 0.0};
+        double pm = 0.0;
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const bool f = (fr >> k) & 1u;
+            if (spend && f) pv[k] += carry[k] * pendc;
+            const double pi = f ? -pv[k] : 0.0;
+            pv[k] = pi;
+            v[0] += pi * g[k];
+            v[1] += isfinite(pi) ? 0.0 : 1.0;
+            pm = fmax(pm, fabs(pi));
+        }
+        block_sum<2, NT>(v, red);
+        if (!(v[0] < 0.0) || v[1] != 0.0) {  // not a finite descent direction: clear memory, -Pg
+            s.npairs = 0;
+            s.newest = -1;
+            used = 0;
+            pm = 0.0;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                pv[k] = ((fr >> k) & 1u) ? -g[k] : 0.0;
+                pm = fmax(pm, fabs(pv[k]));
+            }
+        }
+        pm = block_max<NT>(pm, red[0]);
+        s.alpha = used ? 1.0 : (pm > 1.0 ? 1.0 / pm : 1.0);
+        s.nbt = 0;
+    }
+
+    if (!finish && s.state != ST_DONE) {
+        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y)
+        double v[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int64_t i = (int64_t)k * NT + tid;
+            if (i < K) {
+                double t = y[k] + s.alpha * pv[k];
+                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                ytg[i] = t;
+                xtg[i] = lo[i] + t * (hi[i] - lo[i]);
+                v[0] += g[k] * (t - y[k]);
+            }
+        }
+        block_sum<1, NT>(v, red);
+        s.dec = v[0];
+        s.state = ST_SEARCH;
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t i = (int64_t)k * NT + tid;
+        if (i < K) {
+            yg[i] = y[k];
+            gg[i] = g[k];
+            pgl[i] = pv[k];
+        }
+    }
+    if (finish) {
+        s.status |= finish;
+        s.state = ST_DONE;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a.st[item] = s;
+        if (finish) {
+            a.active[item] = 0;
+            atomicSub(a.nactive, 1);
+        }
+    }
+}
+
 // items stopped by a line-search failure continue from their point (pairs kept) in FP64
 __global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t nitems) {
     const int item = blockIdx.x;
@@ -486,8 +762,10 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
             for (int k = 0; k < o->iters_per_graph && rc == CS_OK; ++k) {
                 rc = launch_eval(p, a.xt, a.active, fe, ge, nullptr, estat, true, mode, s);
                 if (rc == CS_OK) {
-                    if (kmax <= 512)
-                        hipLaunchKernelGGL(k_opt_update<64>, dim3(B), dim3(64), 0, s, a);
+                    if (kmax <= 64 * 8)
+                        hipLaunchKernelGGL((k_opt_update_tile<64, 8>), dim3(B), dim3(64), 0, s, a);
+                    else if (kmax <= 1024 * 8)
+                        hipLaunchKernelGGL((k_opt_update_tile<1024, 8>), dim3(B), dim3(1024), 0, s, a);
                     else
                         hipLaunchKernelGGL(k_opt_update<1024>, dim3(B), dim3(1024), 0, s, a);
                     hipError_t eu = hipGetLastError();

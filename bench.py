@@ -16,6 +16,7 @@ around every launch of that kernel in the timed region), and the FP64 oracle on 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -51,6 +52,18 @@ def algorithmic_bytes(prob, sky, storage_bytes: int) -> float:
     return total
 
 
+def _roctx():
+    """ROC-TX range API (marks the timed region for a profiler run); None if unavailable."""
+    for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so"):
+        try:
+            lib = ctypes.CDLL(name)
+            lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            return lib
+        except OSError:
+            continue
+    return None
+
+
 def measured_traffic(schedule):
     """HBM bytes per launch of the pixel kernel from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by a plain copy's readings), or None unless that summary was taken on the
@@ -68,7 +81,7 @@ def measured_traffic(schedule):
     return rec.get("traffic_bytes_per_launch")
 
 
-def time_eval(prob, x, steps, warmup, timing=True):
+def time_eval(prob, x, steps, warmup, timing=True, label=None):
     out = (torch.empty(prob.nitems, dtype=torch.float64, device="cuda"),
            torch.empty(prob.nparams, dtype=torch.float64, device="cuda"),
            torch.empty(prob.nitems, dtype=torch.int32, device="cuda"))
@@ -77,11 +90,16 @@ def time_eval(prob, x, steps, warmup, timing=True):
     torch.cuda.synchronize()
     prob.set_timing(timing)
     prob.kernel_time()  # reset
+    tx = _roctx() if label else None
+    if tx:
+        tx.roctxRangePushA(label.encode())
     t0 = time.perf_counter()
     for _ in range(steps):
         prob.cs_likelihood_grad(x, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if tx:
+        tx.roctxRangePop()
     kms, nl = prob.kernel_time() if timing else (0.0, 0)
     prob.set_timing(False)
     return (t1 - t0), kms, nl, out
@@ -116,6 +134,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="kernel-profiling run: only the timed evaluations of one precision")
+    ap.add_argument("--profile-optimizer", type=int, default=0, metavar="ITERS",
+                    help="kernel-profiling run: only the batched optimiser, ITERS iterations, one precision")
     ap.add_argument("--precision", default="fp32_bulk", choices=["fp64", "fp32_bulk", "fp32_store"])
     ap.add_argument("--shared-segments", type=int, default=None, choices=[0, 1],
                     help="profiling run: force the per-pixel (0) or segment-shared (1) schedule")
@@ -163,13 +183,28 @@ def main():
         w, b, xr, sh = (int(v) for v in args.schedule.split(","))
         fixed = dict(waves_per_block=w, blocks_per_cu=b, xcd_remap=xr, shared_segments=sh)
 
+    if args.profile_optimizer:
+        prob = cs.Problem.from_sky(sky, args.precision)
+        if fixed:
+            prob.set_schedule(**fixed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = prob.cs_optimize_batch(lo, hi, sky.x_packed(),
+                                   cs.default_opts(max_iter=args.profile_optimizer, fp64_polish=0))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ne = int(r["nevals"].sum().item())
+        print(json.dumps({"precision": args.precision, "optimizer_s": dt, "evals": ne,
+                          "ms_per_step": dt / (ne / sky.nitems) * 1e3}), flush=True)
+        return
+
     if args.profile:
         prob = cs.Problem.from_sky(sky, args.precision)
         if fixed:
             prob.set_schedule(**fixed)
         elif args.shared_segments is not None:
             prob.set_schedule(4, 0, 1, args.shared_segments)
-        wall, kms, nl, _ = time_eval(prob, x, args.steps, args.warmup)
+        wall, kms, nl, _ = time_eval(prob, x, args.steps, args.warmup, label=f"bench_timed_{args.precision}")
         ab = algorithmic_bytes(prob, sky, 8 if args.precision == "fp64" else 4)
         print(json.dumps({"precision": args.precision, "ms_per_step": wall / args.steps * 1e3,
                           "kernel_ms": kms / max(nl, 1), "bytes_per_launch": ab,
@@ -190,7 +225,7 @@ def main():
         sched = dict(waves_per_block=s.waves_per_block, blocks_per_cu=s.blocks_per_cu, xcd_remap=s.xcd_remap,
                      shared_segments=s.shared_segments)
         log(f"autotuned schedule {sched}")
-    wall, kms, nl, out32 = time_eval(p32, x, args.steps, args.warmup)
+    wall, kms, nl, out32 = time_eval(p32, x, args.steps, args.warmup, label="bench_timed_fp32_bulk")
     f32 = out32[0].cpu().numpy()
     g32 = out32[1].cpu().numpy()
     evals = sky.nitems * args.steps

@@ -185,9 +185,17 @@ cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const u
                           int64_t labels_stride, int32_t *keff, void *workspace, size_t bytes,
                           void *stream);
 
-/* Batched projected L-BFGS on the device (internal box y = (x - l)/(u - l), paper App. A.1;
- * bound clamping as in Alg. 1).  Defaults: m = 10, gtol_rel = 1e-8, max_iter = 1000,
- * iters_per_graph = 8, max_backtracks = 30, c1 = 1e-4, fp64_polish = 1. */
+/* Batched bound-constrained optimisers on the device, in the internal box y = (x - l)/(u - l)
+ * (paper App. A.1) with bound clamping as in Alg. 1:
+ *   CS_SOLVER_LBFGS    projected L-BFGS (two-loop recursion on the free set, Armijo backtracking)
+ *   CS_SOLVER_ADATOPK  AdaTopK (App. A): AdaBelief directions, Top-K release of pinned bounds,
+ *                      dynamic rescaling of the objective and moments, step limited by the
+ *                      nearest bound (which is then pinned), backtracking line search
+ * Defaults: solver = L-BFGS, m = 10, gtol_rel = 1e-8, max_iter = 1000, iters_per_graph = 8,
+ * max_backtracks = 30, c1 = 1e-4, fp64_polish = 1, lr = 0.01, beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-16, topk = 0. */
+#define CS_SOLVER_LBFGS 0
+#define CS_SOLVER_ADATOPK 1
 typedef struct {
     int32_t m;               /* history pairs, 1..32                                        */
     double gtol_rel;         /* stop when |P g|_2 <= gtol_rel |P g_0|_2 (internal units)    */
@@ -197,11 +205,17 @@ typedef struct {
     double c1;               /* Armijo constant                                             */
     int32_t fp64_polish;     /* CS_FP32_BULK only: items whose line search fails continue
                                 with FP64 accumulation on the same FP32 data                */
+    int32_t solver;          /* CS_SOLVER_LBFGS or CS_SOLVER_ADATOPK                         */
+    double lr;               /* AdaTopK: AdaBelief step size (internal units)                */
+    double beta1, beta2;     /* AdaTopK: moment decay rates, in [0, 1)                       */
+    double eps;              /* AdaTopK: AdaBelief epsilon, >= 0                             */
+    double topk;             /* AdaTopK: fraction in [0, 1] of the releasable bounds freed per
+                                iteration (at least one)                                     */
 } cs_optim_opts;
 
 cs_status cs_optim_default_opts(cs_optim_opts *opts); /* host */
 
-/* Device workspace of the optimiser for history m. */
+/* Device workspace of the optimiser for history m (AdaTopK uses it with any m >= 1). */
 cs_status cs_optimizer_workspace_bytes(const cs_problem *prob, int32_t m, size_t *bytes);
 
 /* Minimises F per item inside [lower, upper] (packed like x, lower < upper).  x: in = start

@@ -10,6 +10,8 @@ from ._lib import (  # noqa: F401
     MAXITER,
     NONFINITE,
     NOT_PD,
+    SOLVER_ADATOPK,
+    SOLVER_LBFGS,
     CsError,
     Problem,
     default_opts,

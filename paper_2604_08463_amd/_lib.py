@@ -45,7 +45,12 @@ class Desc(C.Structure):
 
 class OptimOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("gtol_rel", C.c_double), ("max_iter", C.c_int32), ("iters_per_graph", C.c_int32),
-                ("max_backtracks", C.c_int32), ("c1", C.c_double), ("fp64_polish", C.c_int32)]
+                ("max_backtracks", C.c_int32), ("c1", C.c_double), ("fp64_polish", C.c_int32),
+                ("solver", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("topk", C.c_double)]
+
+
+SOLVER_LBFGS, SOLVER_ADATOPK = 0, 1
 
 
 class Schedule(C.Structure):

@@ -418,6 +418,12 @@ cs_status cs_optim_default_opts(cs_optim_opts *o) {
     o->max_backtracks = 30;
     o->c1 = 1e-4;
     o->fp64_polish = 1;
+    o->solver = CS_SOLVER_LBFGS;
+    o->lr = 0.01;
+    o->beta1 = 0.9;
+    o->beta2 = 0.999;
+    o->eps = 1e-16;
+    o->topk = 0.0;
     return CS_OK;
 }
 
@@ -434,6 +440,11 @@ cs_status cs_optimize_batch(cs_problem *p, const cs_optim_opts *o, const double 
     if (o->m < 1 || o->m > 32 || o->max_iter < 0 || o->iters_per_graph < 1 || o->iters_per_graph > 4096 ||
         o->max_backtracks < 0 || !(o->c1 > 0.0 && o->c1 < 1.0) || !(o->gtol_rel >= 0.0))
         return invalid("bad optimiser options");
+    if (o->solver != CS_SOLVER_LBFGS && o->solver != CS_SOLVER_ADATOPK) return invalid("unknown solver");
+    if (o->solver == CS_SOLVER_ADATOPK &&
+        (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) || !(o->beta2 >= 0.0 && o->beta2 < 1.0) ||
+         !(o->eps >= 0.0) || !(o->topk >= 0.0 && o->topk <= 1.0)))
+        return invalid("bad AdaTopK options");
     if (!p->prepared) {
         set_error("cs_problem_prepare has not completed");
         return CS_E_STATE;

@@ -1,4 +1,5 @@
-// Batched projected L-BFGS on the device (a8), driven by HIP-graph replays (a9).
+// Batched bound-constrained optimisers on the device (a8): projected L-BFGS and AdaTopK, driven by
+// HIP-graph replays (a9).
 //
 // Every item (realization / configuration) runs its own optimisation in the internal box
 // y = (x - l)/(u - l) in [0,1]^K (paper App. A.1); trial points are clamped to the box, the
@@ -24,6 +25,9 @@ struct OptItem {
     double f, pg0, alpha, dec;
     int64_t nevals;
     int32_t state, status, iter, nbt, npairs, newest, pad0, pad1;
+    // AdaTopK: objective scale, bias-correction powers, last accepted step, step limit
+    double scale, b1t, b2t, aprev, amax;
+    int32_t t, lim, hit, pad2;
 };
 
 struct OptArgs {
@@ -38,8 +42,10 @@ struct OptArgs {
     const double *lo, *hi;
     const int64_t *xoff;
     int64_t ktot;
-    int32_t m, max_iter, max_backtracks, pad;
+    int32_t m, max_iter, max_backtracks, solver;
     double gtol, c1;
+    int32_t *piv;  // [Ktot] AdaTopK pivots: -1 lower bound, +1 upper bound, 0 free
+    double lr, b1, b2, eps, topk;
 };
 
 constexpr int kOptThreads = 256;   // block size of the small per-item kernels
@@ -101,10 +107,20 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_init(OptArgs a, const doubl
         a.y[o + i] = yi;
         a.yt[o + i] = yi;
         a.xt[o + i] = l + yi * (u - l);
+        if (a.solver == CS_SOLVER_ADATOPK) {
+            a.piv[o + i] = yi <= 0.0 ? -1 : (yi >= 1.0 ? 1 : 0);
+            a.S[o + i] = 0.0;  // first moment
+            a.T[o + i] = 0.0;  // second moment
+        }
     }
     if (threadIdx.x == 0) {
         OptItem s{};
         s.state = ST_INIT;
+        s.scale = 1.0;
+        s.b1t = 1.0;
+        s.b2t = 1.0;
+        s.aprev = 1.0;
+        s.lim = -1;
         a.st[item] = s;
         a.active[item] = 1;
         if (item == 0) *a.nactive = nitems;
@@ -621,11 +637,274 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// AdaTopK (paper App. A), one workgroup per item.  Each iteration: release the pinned bounds whose
+// descent direction points into the box (the largest scores p_i g_i, max(1, floor(topk n)) of
+// them), stop on the projected-gradient test, rescale the objective and the moments when the
+// scaled gradient norm leaves [1e-15, 1e15], take the AdaBelief direction on the free set, limit
+// the step by the nearest bound (pinning it at once when the limit is zero), then backtrack from
+// min(limit, 1, 2 x last step): Armijo for a descent step, a strict decrease otherwise, or the flat-F
+// rule.  A failed search resets the moments once; a failure with fresh moments stops the item.
+// ---------------------------------------------------------------------------------------------
+// best (value, index) over a workgroup: the largest value (kMax) or the smallest, ties to the
+// lowest index; every thread receives the result
+template <int NT, bool kMax>
+__device__ __forceinline__ void block_best(double &v, int64_t &idx, double *shv, int64_t *shi) {
+    constexpr int NWV = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto better = [](double va, int64_t ia, double vb, int64_t ib) {
+        if (ib < 0) return false;
+        if (ia < 0) return true;
+        if (kMax ? (vb > va) : (vb < va)) return true;
+        return vb == va && ib < ia;
+    };
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int64_t oi = __shfl_xor(idx, off, 64);
+        if (better(v, idx, ov, oi)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+    if (NWV == 1) return;
+    if (lane == 0) {
+        shv[wave] = v;
+        shi[wave] = idx;
+    }
+    __syncthreads();
+    v = shv[0];
+    idx = shi[0];
+    for (int w = 1; w < NWV; ++w)
+        if (better(v, idx, shv[w], shi[w])) {
+            v = shv[w];
+            idx = shi[w];
+        }
+    __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ada_update(OptArgs a) {
+    const int item = blockIdx.x;
+    if (!a.active[item]) return;
+    __shared__ double red[8][16];
+    __shared__ double bv[16];
+    __shared__ int64_t bi[16];
+    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    const int tid = threadIdx.x;
+    const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
+    double *y = a.y + o, *g = a.g + o, *d = a.p + o, *yt = a.yt + o, *xt = a.xt + o;
+    double *mm = a.S + o, *vv = a.T + o;
+    int32_t *piv = a.piv + o;
+    OptItem s = a.st[item];  // every thread holds the same copy
+    s.nevals += 1;
+    const double fe = a.fe[item];
+    const int32_t est = a.estat[item];
+    const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
+    int32_t finish = 0;
+    bool iterate = false;  // start a new iteration from the current point
+
+    if (s.state == ST_INIT || s.state == ST_REINIT) {
+        if (!evalok) {
+            finish = est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE);
+            if (!finish) finish = CS_ITEM_NONFINITE;
+        } else {
+            for (int64_t i = tid; i < K; i += NT) g[i] = ge[i] * (hi[i] - lo[i]);
+            s.f = fe;
+            iterate = true;
+        }
+    } else if (s.state == ST_SEARCH) {
+        // g.(y_t - y), |y_t - y|^2 and g_t.(y_t - y) at the evaluated trial
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int64_t i = tid; i < K; i += NT) {
+            const double st = yt[i] - y[i];
+            v[0] += g[i] * st;
+            v[1] += st * st;
+            v[2] += ge[i] * (hi[i] - lo[i]) * st;
+        }
+        block_sum<3, NT>(v, red);
+        bool ok = false;
+        if (evalok && v[1] > 0.0) {
+            const bool dec_ok = v[0] < 0.0 ? (fe <= s.f + a.c1 * v[0]) : (fe < s.f);
+            ok = dec_ok || (fabs(fe - s.f) <= kFlatRel * fabs(s.f) && v[2] <= 0.0);
+        }
+        if (ok) {
+            s.aprev = s.alpha;
+            for (int64_t i = tid; i < K; i += NT) {
+                y[i] = yt[i];
+                g[i] = ge[i] * (hi[i] - lo[i]);
+            }
+            if (s.hit && tid == 0) piv[s.lim] = d[s.lim] > 0.0 ? 1 : -1;
+            s.f = fe;
+            s.iter += 1;
+            iterate = true;
+        } else {
+            s.nbt += 1;
+            if (s.nbt > a.max_backtracks) {
+                if (s.t <= 1) {
+                    finish = CS_ITEM_LS_FAIL;
+                } else {  // reset the moments once and start again from the same point
+                    for (int64_t i = tid; i < K; i += NT) {
+                        mm[i] = 0.0;
+                        vv[i] = 0.0;
+                    }
+                    s.t = 0;
+                    s.b1t = s.b2t = 1.0;
+                    s.aprev = 1.0;
+                    s.iter += 1;
+                    iterate = true;
+                }
+            } else {
+                s.alpha *= 0.5;
+                s.hit = (s.lim >= 0 && s.alpha == s.amax) ? 1 : 0;
+            }
+        }
+    }
+    __syncthreads();  // pivot and point updates visible to the whole workgroup
+
+    bool trial = !finish && s.state == ST_SEARCH && !iterate;  // a halved step of the same direction
+    while (iterate && !finish) {
+        // 1. Top-K release among the pinned coordinates with a positive score p_i g_i
+        double cnt[1] = {0.0};
+        for (int64_t i = tid; i < K; i += NT)
+            if (piv[i] != 0 && piv[i] * g[i] > 0.0) cnt[0] += 1.0;
+        block_sum<1, NT>(cnt, red);
+        const int64_t ncand = (int64_t)cnt[0];
+        if (ncand > 0) {
+            int64_t nrel = (int64_t)floor(a.topk * (double)ncand);
+            if (nrel < 1) nrel = 1;
+            if (nrel >= ncand) {
+                for (int64_t i = tid; i < K; i += NT)
+                    if (piv[i] != 0 && piv[i] * g[i] > 0.0) piv[i] = 0;
+            } else {
+                for (int64_t r = 0; r < nrel; ++r) {
+                    double bvv = 0.0;
+                    int64_t bix = -1;
+                    for (int64_t i = tid; i < K; i += NT)
+                        if (piv[i] != 0 && piv[i] * g[i] > 0.0) {
+                            const double sc = piv[i] * g[i];
+                            if (bix < 0 || sc > bvv) {
+                                bvv = sc;
+                                bix = i;
+                            }
+                        }
+                    block_best<NT, true>(bvv, bix, bv, bi);
+                    if (bix < 0) break;
+                    if (tid == 0) piv[bix] = 0;
+                    __syncthreads();
+                }
+            }
+        }
+        __syncthreads();
+        // 2. projected gradient and the stopping tests
+        double pg[1] = {0.0};
+        for (int64_t i = tid; i < K; i += NT)
+            if (piv[i] == 0) pg[0] += g[i] * g[i];
+        block_sum<1, NT>(pg, red);
+        const double pgn = sqrt(pg[0]);
+        if (s.state == ST_INIT) {
+            s.pg0 = pgn;
+            if (!isfinite(pgn)) {
+                finish = CS_ITEM_NONFINITE;
+                break;
+            }
+        }
+        if (pgn <= a.gtol * s.pg0) {
+            finish = CS_ITEM_CONVERGED;
+            break;
+        }
+        if (s.iter >= a.max_iter) {
+            finish = CS_ITEM_MAXITER;
+            break;
+        }
+        s.state = ST_SEARCH;  // any later pass of this loop is a continuation
+        // 3. rescaling of the objective scale and the moments
+        const double cpg = s.scale * pgn;
+        double fs = 1.0;
+        if (cpg < 1e-15 || cpg > 1e15) {
+            fs = 1.0 / cpg;
+            s.scale *= fs;
+        }
+        // 4. AdaBelief on the scaled projected gradient; 5. distance to the nearest bound
+        s.t += 1;
+        s.b1t *= a.b1;
+        s.b2t *= a.b2;
+        double amin = 0.0;
+        int64_t lim = -1;
+        for (int64_t i = tid; i < K; i += NT) {
+            double m = mm[i], v = vv[i];
+            if (fs != 1.0) {
+                m *= fs;
+                v *= fs * fs;
+            }
+            const double gi = piv[i] != 0 ? 0.0 : s.scale * g[i];
+            m = a.b1 * m + (1.0 - a.b1) * gi;
+            const double dv = gi - m;
+            v = a.b2 * v + (1.0 - a.b2) * dv * dv + a.eps;
+            mm[i] = m;
+            vv[i] = v;
+            const double mh = m / (1.0 - s.b1t), vh = v / (1.0 - s.b2t);
+            const double di = piv[i] != 0 ? 0.0 : -a.lr * mh / (sqrt(vh) + a.eps);
+            d[i] = di;
+            if (piv[i] == 0 && di != 0.0) {
+                const double ai = di > 0.0 ? (1.0 - y[i]) / di : -y[i] / di;
+                if (lim < 0 || ai < amin) {
+                    amin = ai;
+                    lim = i;
+                }
+            }
+        }
+        block_best<NT, false>(amin, lim, bv, bi);
+        s.amax = lim >= 0 ? amin : INFINITY;
+        s.lim = (int32_t)lim;
+        __syncthreads();  // d complete before any thread reads another's entry
+        if (lim >= 0 && amin <= 0.0) {  // zero step to the bound: pin it without an evaluation
+            if (tid == 0) {
+                const bool up = d[lim] > 0.0;
+                piv[lim] = up ? 1 : -1;
+                y[lim] = up ? 1.0 : 0.0;
+            }
+            s.iter += 1;
+            __syncthreads();
+            continue;
+        }
+        // 6. first trial step
+        const double a0 = 2.0 * s.aprev < 1.0 ? 2.0 * s.aprev : 1.0;
+        s.alpha = s.amax < a0 ? s.amax : a0;
+        s.hit = (lim >= 0 && s.alpha == s.amax) ? 1 : 0;
+        s.nbt = 0;
+        trial = true;
+        break;
+    }
+
+    if (finish) {
+        s.status |= finish;
+        s.state = ST_DONE;
+    } else if (trial) {
+        for (int64_t i = tid; i < K; i += NT) {
+            double t = y[i] + s.alpha * d[i];
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            if (s.hit && i == s.lim) t = d[i] > 0.0 ? 1.0 : 0.0;
+            yt[i] = t;
+            xt[i] = lo[i] + t * (hi[i] - lo[i]);
+        }
+        s.state = ST_SEARCH;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a.st[item] = s;
+        if (finish) {
+            a.active[item] = 0;
+            atomicSub(a.nactive, 1);
+        }
+    }
+}
+
 // items stopped by a line-search failure continue from their point (pairs kept) in FP64
 __global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t nitems) {
     const int item = blockIdx.x;
-    OptItem s = a.st[item];
-    if (!(s.state == ST_DONE && (s.status & CS_ITEM_LS_FAIL))) return;
+    OptItem *s = a.st + item;
+    if (!(s->state == ST_DONE && (s->status & CS_ITEM_LS_FAIL))) return;
     const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
     for (int64_t i = threadIdx.x; i < K; i += blockDim.x) {
         a.yt[o + i] = a.y[o + i];
@@ -633,9 +912,8 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        s.status &= ~CS_ITEM_LS_FAIL;
-        s.state = ST_REINIT;
-        a.st[item] = s;
+        s->status &= ~CS_ITEM_LS_FAIL;
+        s->state = ST_REINIT;
         a.active[item] = 1;
         atomicAdd(a.nactive, 1);
     }
@@ -672,6 +950,7 @@ size_t optimizer_bytes(const cs_problem *p, int32_t m) {
     t += al256(sizeof(double) * B);
     t += al256(sizeof(double) * K) * 6;
     t += al256(sizeof(double) * K * (size_t)m) * 2;
+    t += al256(sizeof(int32_t) * K);  // AdaTopK pivots
     return t;
 }
 
@@ -709,6 +988,7 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
     a.xt = (double *)take(sizeof(double) * K);
     a.S = (double *)take(sizeof(double) * K * o->m);
     a.T = (double *)take(sizeof(double) * K * o->m);
+    a.piv = (int32_t *)take(sizeof(int32_t) * K);
     a.lo = lo;
     a.hi = hi;
     a.xoff = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)B);
@@ -718,6 +998,12 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
     a.max_backtracks = o->max_backtracks;
     a.gtol = o->gtol_rel;
     a.c1 = o->c1;
+    a.solver = o->solver;
+    a.lr = o->lr;
+    a.b1 = o->beta1;
+    a.b2 = o->beta2;
+    a.eps = o->eps;
+    a.topk = o->topk;
 
     CSI_HIP(hipStreamSynchronize(caller));
     hipStream_t s;
@@ -762,7 +1048,11 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
             for (int k = 0; k < o->iters_per_graph && rc == CS_OK; ++k) {
                 rc = launch_eval(p, a.xt, a.active, fe, ge, nullptr, estat, true, mode, s);
                 if (rc == CS_OK) {
-                    if (kmax <= 64 * 8)
+                    if (o->solver == CS_SOLVER_ADATOPK && kmax <= 1024)
+                        hipLaunchKernelGGL(k_ada_update<256>, dim3(B), dim3(256), 0, s, a);
+                    else if (o->solver == CS_SOLVER_ADATOPK)
+                        hipLaunchKernelGGL(k_ada_update<1024>, dim3(B), dim3(1024), 0, s, a);
+                    else if (kmax <= 64 * 8)
                         hipLaunchKernelGGL((k_opt_update_tile<64, 8>), dim3(B), dim3(64), 0, s, a);
                     else if (kmax <= 1024 * 8)
                         hipLaunchKernelGGL((k_opt_update_tile<1024, 8>), dim3(B), dim3(1024), 0, s, a);

@@ -134,6 +134,8 @@ def test_optimizer_options_validation(lib):
     assert lib.cs_optim_default_opts(C.byref(o)) == 0
     assert (o.m, o.max_iter, o.iters_per_graph, o.max_backtracks, o.fp64_polish) == (10, 1000, 8, 30, 1)
     assert o.gtol_rel == 1e-8 and o.c1 == 1e-4
+    assert o.solver == _lib.SOLVER_LBFGS
+    assert (o.lr, o.beta1, o.beta2, o.eps, o.topk) == (0.01, 0.9, 0.999, 1e-16, 0.0)
 
 
 def test_schedule_validation(lib):

@@ -1,0 +1,112 @@
+"""GPU AdaTopK (cs_optimize_batch with the AdaTopK solver) against the oracle's AdaTopK.
+
+Both follow the same iteration; block reductions on the device round differently from the
+oracle's sequential sums, so trajectories can part at the rounding level.  Parity is therefore
+on the result: the converged parameters within 1e-4 max(1, |x|) and F within 1e-10 relative, as
+for the L-BFGS.  A parameter pinned on a bound must sit exactly on it.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import skygen
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+cs = pytest.importorskip("paper_2604_08463_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cs.load()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _run(prob, lo, hi, x0, **kw):
+    o = cs.default_opts(solver=cs.SOLVER_ADATOPK, **kw)
+    r = prob.cs_optimize_batch(lo, hi, x0, o)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def test_adatopk_matches_oracle_tiny_items():
+    sky = skygen.make_tiny(16, 15, (2, 1, 1), seed=16, model_consistent=True, nitems=3)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    x0 = np.tile(np.array([1.54, 1.54, 20.0, -3.0]), sky.nitems)
+    r = _run(prob, lo, hi, x0, max_iter=3000)
+    off = sky.param_offsets()
+    for b in range(sky.nitems):
+        xo, fo, ito, _, sto = oracle.Problem.from_sky(sky, b).adatopk(x0[off[b]:off[b + 1]], lo[off[b]:off[b + 1]],
+                                                                     hi[off[b]:off[b + 1]], max_iter=3000)
+        xb = r["x"][off[b]:off[b + 1]]
+        _log(f"item {b}: gpu F {r['f'][b]:.12g} st {r['status'][b]} it {r['iters'][b]}  oracle F {fo:.12g} st {sto} it {ito}")
+        assert r["status"][b] & cs.CONVERGED and sto & oracle.CONVERGED
+        assert abs(r["f"][b] - fo) <= 1e-10 * abs(fo)
+        assert np.all(np.abs(xb - xo) <= 1e-4 * np.maximum(1.0, np.abs(xo)))
+
+
+def test_adatopk_pins_active_bound_exactly():
+    sky = skygen.make_tiny(16, 15, (1, 1, 1), seed=19, model_consistent=True, noiseless=True)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    hi = hi.copy()
+    hi[0] = sky.x[0][0] - 0.2  # beta_d bound below its true value
+    x0 = np.array(skygen.X0)
+    r = _run(prob, lo, hi, x0, max_iter=3000)
+    xo, fo, _, _, sto = oracle.Problem.from_sky(sky).adatopk(x0, lo, hi, max_iter=3000)
+    assert r["status"][0] & cs.CONVERGED and sto & oracle.CONVERGED
+    assert r["x"][0] == hi[0] and xo[0] == hi[0]
+    assert np.all(np.abs(r["x"] - xo) <= 1e-4 * np.maximum(1.0, np.abs(xo)))
+
+
+@pytest.mark.parametrize("topk", [0.0, 1.0])
+def test_adatopk_from_bounds_matches_oracle(topk):
+    # every parameter starts pinned at its lower bound; release fractions 0 (one per iteration)
+    # and 1 (all releasable at once).  From this start item 1 settles in a shallower local minimum
+    # than the L-BFGS from the usual start, in the oracle as on the device, so the reference is
+    # the oracle's AdaTopK from the same start.
+    sky = skygen.make_tiny(64, 15, (3, 2, 2), seed=17, nitems=2)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = _run(prob, lo, hi, lo.copy(), topk=topk, max_iter=5000)
+    off = sky.param_offsets()
+    for b in range(sky.nitems):
+        sl = slice(off[b], off[b + 1])
+        xo, fo, ito, _, sto = oracle.Problem.from_sky(sky, b).adatopk(lo[sl].copy(), lo[sl], hi[sl], topk=topk,
+                                                                     max_iter=5000)
+        _log(f"topk {topk} item {b}: gpu F {r['f'][b]:.12g} st {r['status'][b]} it {r['iters'][b]}  "
+             f"oracle F {fo:.12g} st {sto} it {ito}")
+        assert r["status"][b] & cs.CONVERGED and sto & oracle.CONVERGED
+        assert abs(r["f"][b] - fo) <= 1e-10 * abs(fo)
+        assert np.all(np.abs(r["x"][sl] - xo) <= 1e-4 * np.maximum(1.0, np.abs(xo)))
+
+
+def test_adatopk_workload3_items_reach_lbfgs_optimum():
+    sky = skygen.make_config(3, nitems=8, device="cuda")
+    lo, hi = sky.bounds_packed()
+    prob = cs.Problem.from_sky(sky, "fp64")
+    x_l = prob.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts())["x"].cpu().numpy()
+    r = _run(prob, lo, hi, sky.x_packed(), max_iter=4000)
+    _log(f"workload 3: status {r['status']} iters {r['iters']} evals {r['nevals']}")
+    assert np.all(r["status"] & cs.CONVERGED)
+    assert np.all(np.abs(r["x"] - x_l) <= 1e-4 * np.maximum(1.0, np.abs(x_l)))
+
+
+def test_adatopk_bad_options_rejected():
+    sky = skygen.make_tiny(16, 15, (1, 1, 1), seed=3)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    for kw in (dict(lr=0.0), dict(beta1=1.0), dict(topk=1.5), dict(solver=7)):
+        o = cs.default_opts(solver=cs.SOLVER_ADATOPK)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        with pytest.raises(cs.CsError):
+            prob.cs_optimize_batch(lo, hi, sky.x_packed(), o)

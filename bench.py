@@ -7,7 +7,7 @@ likelihood + gradient evaluation of every realization (SED tables, fused per-pix
 per-cluster reductions); `value` counts evaluations (one item: -2 ln L and its full gradient)
 per second with the data already resident in HBM.  The same run also reports the plain FP64
 GPU path, the FP32-vs-FP64 error of every result, the once-per-clustering preparation time, the
-batched on-device projected L-BFGS, the per-pixel kernel against the HBM roofline (HIP events
+batched on-device projected L-BFGS and AdaTopK, the per-pixel kernel against the HBM roofline (HIP events
 around every launch of that kernel in the timed region), and the FP64 oracle on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-optimizer]
@@ -261,6 +261,7 @@ def main():
         torch.cuda.empty_cache()
 
     opt = None
+    opt_ada = None
     if not args.no_optimizer:
         p32 = cs.Problem.from_sky(sky, "fp32_bulk")
         if sched:
@@ -272,11 +273,23 @@ def main():
         dt = time.perf_counter() - t1
         st = r["status"].cpu().numpy()
         ne = r["nevals"].cpu().numpy()
-        opt = dict(time_s=dt, evals=int(ne.sum()), evals_per_s=float(ne.sum() / dt),
+        opt = dict(solver="projected L-BFGS", time_s=dt, evals=int(ne.sum()), evals_per_s=float(ne.sum() / dt),
                    iters_median=float(np.median(r["iters"].cpu().numpy())),
                    converged=int(np.sum(st & cs.CONVERGED > 0)), ls_fail=int(np.sum(st & cs.LS_FAIL > 0)),
-                   maxiter=int(np.sum(st & cs.MAXITER > 0)))
+                   maxiter=int(np.sum(st & cs.MAXITER > 0)), f_mean=float(r["f"].mean().item()))
         log(f"optimizer: {opt}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = p32.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts(max_iter=1000, solver=cs.SOLVER_ADATOPK))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        st = r["status"].cpu().numpy()
+        ne = r["nevals"].cpu().numpy()
+        opt_ada = dict(solver="AdaTopK", time_s=dt, evals=int(ne.sum()), evals_per_s=float(ne.sum() / dt),
+                       iters_median=float(np.median(r["iters"].cpu().numpy())),
+                       converged=int(np.sum(st & cs.CONVERGED > 0)), ls_fail=int(np.sum(st & cs.LS_FAIL > 0)),
+                       maxiter=int(np.sum(st & cs.MAXITER > 0)), f_mean=float(r["f"].mean().item()))
+        log(f"optimizer (AdaTopK): {opt_ada}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -313,6 +326,7 @@ def main():
         "fp32_vs_fp64": err,
         "prep_ms": prep_ms,
         "optimizer": opt,
+        "optimizer_adatopk": opt_ada,
     }
     print(json.dumps(line), flush=True)
 

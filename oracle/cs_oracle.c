@@ -148,12 +148,17 @@ static int orc_lu_solve3(const double m[9], const double b[3], double xout[3]) {
 }
 
 /* positive definiteness by Sylvester's criterion: all leading principal minors > 0 */
+/* Positive definiteness of the symmetric 3x3 M (Sylvester's criterion, read numerically): each
+ * leading principal minor must be positive relative to the product of its diagonal entries,
+ * minor_k > ORC_PD_REL * m_00 ... m_kk, so that a rank-deficient M (fewer bands than components,
+ * or degenerate columns) is flagged whatever sign rounding gives its determinant. */
+#define ORC_PD_REL 1e-12
 static int orc_is_pd3(const double m[9]) {
     double m1 = m[0];
     double m2 = m[0] * m[4] - m[1] * m[3];
     double m3 = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
                 m[2] * (m[3] * m[7] - m[4] * m[6]);
-    return m1 > 0.0 && m2 > 0.0 && m3 > 0.0;
+    return m1 > 0.0 && m2 > ORC_PD_REL * m[0] * m[4] && m3 > ORC_PD_REL * m[0] * m[4] * m[8];
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -83,6 +83,16 @@ __global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xo
     }
 }
 
+// Positive definiteness of M = A^T N^-1 A from its Cholesky pivots m00, p1, p2: the leading
+// principal minors m00, m00 p1 and m00 p1 p2 must be positive relative to the products of their
+// diagonal entries (p1 / m11 and p1 p2 / (m11 m22) above a tolerance of the accumulation
+// precision), so that a rank-deficient M is flagged whatever sign rounding gives its last pivot.
+template <typename TA>
+__device__ __forceinline__ bool pd_pivots(double m00, double m11, double m22, double p1, double p2) {
+    constexpr double kTau = sizeof(TA) == 4 ? 1e-6 : 1e-12;
+    return m00 > 0.0 && p1 > kTau * m11 && p1 * p2 > kTau * m11 * m22;
+}
+
 // ---------------------------------------------------------------------------------------------
 // a3-a7 (first level): the per-pixel kernel
 // ---------------------------------------------------------------------------------------------
@@ -331,7 +341,7 @@ __device__ __forceinline__ void unit_pixel(const EvalArgs &a, const int item, co
             const double p2 = m22 - l20 * l20 - l21 * l21;
             const double l22 = sqrt(p2);
             const double i22 = 1.0 / l22;
-            ok = ok && (m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+            ok = ok && pd_pivots<TA>(m00, m11, m22, p1, p2);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (NW == 2 && s != n) continue;
@@ -612,7 +622,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             r.l21 = (m12 - r.l20 * r.l10) * r.i11;
             const double p2 = m22 - r.l20 * r.l20 - r.l21 * r.l21;
             r.i22 = 1.0 / sqrt(p2);
-            r.ok = ((m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0)) ? 1.0 : 0.0;
+            r.ok = pd_pivots<TA>(m00, m11, m22, p1, p2) ? 1.0 : 0.0;
             r.g01 = P.g01;
             r.g02 = P.g02;
             r.g03 = P.g03;
@@ -735,7 +745,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         l21 = (m12 - l20 * l10) * i11;
         const double p2 = m22 - l20 * l20 - l21 * l21;
         i22 = 1.0 / sqrt(p2);
-        ok = (m00 > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+        ok = pd_pivots<TA>(m00, m11, m22, p1, p2);
         G[0] = A.g01; G[1] = A.g02; G[2] = A.g03;
         G[3] = A.g11; G[4] = A.g12; G[5] = A.g13;
         G[6] = A.g21; G[7] = A.g22; G[8] = A.g23;

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
         const double l21 = (c[4] - l20 * l10) / l11;
         const double p2 = c[5] - l20 * l20 - l21 * l21;
         const double l22 = sqrt(p2);
-        ok = ok && (c[0] > 0.0) && (p1 > 0.0) && (p2 > 0.0);
+        ok = ok && c[0] > 0.0 && p1 > 1e-12 * c[3] && p1 * p2 > 1e-12 * c[3] * c[5];  // relative minors
         const double z0 = b[s][0] / l00;
         const double z1 = (b[s][1] - l10 * z0) / l11;
         const double z2 = (b[s][2] - l20 * z0 - l21 * z1) / l22;

@@ -1,0 +1,81 @@
+"""Edge cases of the HIP path against the oracle: an item whose pixels are all excluded, a
+single-pixel sky, fewer bands than components (every pixel degenerate), and one cluster per pixel
+(every chunk takes the direct-gather path)."""
+
+import numpy as np
+import pytest
+import torch
+
+import skygen
+from oracle import oracle
+from tests._parity import compare, gpu_eval
+
+pytestmark = pytest.mark.gpu
+
+cs = pytest.importorskip("paper_2604_08463_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cs.load()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def test_item_with_every_pixel_excluded():
+    sky = skygen.make_tiny(300, 15, (4, 2, 3), seed=51, nitems=2)
+    lab = sky.item_labels(0)
+    labels = np.stack([lab, np.full_like(lab, -1)])  # item 1 keeps no pixel
+    prob = cs.Problem(sky.freqs, sky.d.cuda(), sky.ninv, torch.as_tensor(labels).cuda(), sky.nclusters,
+                      nitems=2, precision="fp64")
+    assert prob.item_info(1) == (0, 0)
+    x = torch.as_tensor(sky.x_packed(), device="cuda")
+    f, g, cf, st = prob.cs_likelihood_grad(x, cluster=True)
+    torch.cuda.synchronize()
+    off = sky.param_offsets()
+    fo, go, co, so = oracle.Problem(sky.freqs, sky.item_d(0), sky.ninv, lab, sky.nclusters[0]).likelihood_grad(sky.x[0])
+    assert abs(f[0].item() - fo) <= 1e-12 * abs(fo)
+    assert f[1].item() == 0.0 and st[1].item() == 0
+    assert torch.all(g[off[1]:off[2]] == 0) and torch.all(cf[off[1]:off[2]] == 0)
+    # component maps: nothing included -> NaN maps and NaN variance for that item
+    m, v, _ = prob.cs_component_maps(x)
+    torch.cuda.synchronize()
+    assert torch.all(torch.isnan(m[1])) and torch.isnan(v[1]) and torch.isfinite(v[0])
+    # optimiser: a zero projected gradient converges at once, the start point unchanged
+    lo, hi = sky.bounds_packed()
+    r = prob.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts())
+    torch.cuda.synchronize()
+    assert r["status"][1].item() & cs.CONVERGED and r["iters"][1].item() == 0
+    assert np.allclose(r["x"][off[1]:off[2]].cpu().numpy(), sky.x[1], rtol=0, atol=1e-12)
+
+
+def test_single_pixel_sky():
+    sky = skygen.make_tiny(1, 15, (1, 1, 1), seed=52, nitems=3)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    compare(sky, prob, "fp64")
+    prob32 = cs.Problem.from_sky(sky, "fp32_bulk")
+    compare(sky, prob32, "fp32_bulk")
+
+
+def test_fewer_bands_than_components_is_degenerate_everywhere():
+    # two bands cannot separate three components: A^T N^-1 A is singular at every pixel
+    sky = skygen.make_tiny(100, 2, (1, 1, 1), seed=53)
+    prob = cs.Problem.from_sky(sky, "fp64")
+    f, g, _, st = gpu_eval(prob, sky, cluster=False)
+    _, _, _, so = oracle.Problem.from_sky(sky).likelihood_grad(sky.x[0])
+    assert so & oracle.NOT_PD and st[0] & cs.NOT_PD and np.isnan(f[0])
+
+
+def test_one_cluster_per_pixel():
+    # as many beta_d clusters as pixels: every 64-pixel chunk holds 64 segments
+    sky = skygen.make_tiny(200, 15, (200, 3, 2), seed=54, nitems=2)
+    assert len(np.unique(sky.item_labels(0)[0])) == 200
+    for precision in ("fp64", "fp32_bulk"):
+        prob = cs.Problem.from_sky(sky, precision)
+        for sh in (0, 1):
+            prob.set_schedule(4, 0, 1, sh)
+            compare(sky, prob, precision)

@@ -664,3 +664,14 @@ def test_adatopk_release_fraction_reaches_the_same_optimum():
         x, f, it, ne, st = pr.adatopk(x0, lo, hi, topk=topk, max_iter=5000)
         assert st & O.CONVERGED, (topk, st)
         assert np.all(np.abs(x - x_ref) <= 1e-4 * np.maximum(1.0, np.abs(x_ref))), topk
+
+
+def test_fewer_bands_than_components_is_not_positive_definite():
+    # with two bands the 3x3 matrix A^T N^-1 A has rank 2 at every pixel; with three or more
+    # generic bands it is positive definite
+    for nfreq, singular in ((2, True), (3, False), (4, False)):
+        sky = skygen.make_tiny(20, nfreq, (1, 1, 1), seed=55)
+        pr = O.Problem.from_sky(sky)
+        for p in range(20):
+            st = pr.pixel(sky.x[0], p)["status"]
+            assert bool(st & O.NOT_PD) == singular, (nfreq, p)

@@ -355,3 +355,27 @@ def test_fp32_bulk_optimum_within_1e4_reduced_workload5():
     _log(f"  max |x32 - x64| {np.max(np.abs(x32 - x64)):.3e}")
     assert np.all(st64 & cs.CONVERGED)
     assert np.all(np.abs(x32 - x64) <= 1e-4 * np.maximum(1.0, np.abs(x64)))
+
+
+def test_workload5_full_size_sampled_items():
+    # the benchmark's workload at full size and in its launch configuration (autotuned schedule):
+    # every item evaluated on the device, two sampled items recomputed by the oracle
+    sky = skygen.make_config(5, device="cuda")
+    x = torch.as_tensor(sky.x_packed(), device="cuda")
+    off = sky.param_offsets()
+    picks = (0, 37)
+    ref = {b: oracle.Problem.from_sky(sky, b).likelihood_grad(sky.x[b]) for b in picks}
+    for precision, tf, tg in (("fp32_bulk", 1e-5, 1e-2), ("fp64", 1e-12, 1e-9)):
+        prob = cs.Problem.from_sky(sky, precision)
+        s = prob.autotune(x, reps=1)
+        f, g, _, st = gpu_eval(prob, sky, cluster=False)
+        for b in picks:
+            fo, go, _, so = ref[b]
+            ef = abs(f[b] - fo) / abs(fo)
+            eg = np.max(np.abs(g[off[b]:off[b + 1]] - go)) / np.max(np.abs(go))
+            _log(f"workload 5 {precision} schedule ({s.waves_per_block},{s.blocks_per_cu},{s.xcd_remap},"
+                 f"{s.shared_segments}) item {b}: rel F {ef:.2e} grad {eg:.2e}")
+            assert st[b] == so and ef <= tf and eg <= tg
+        assert np.all(np.isfinite(f)) and np.all(st == 0)
+        del prob
+        torch.cuda.empty_cache()

@@ -52,34 +52,40 @@ struct Band<float> {
 // ---------------------------------------------------------------------------------------------
 // Grid: x over an item's (parameter, band) pairs, y over items (from item0): the item is uniform
 // in a workgroup, so its descriptor comes through the scalar cache.
+constexpr int kSedBands = 4;  // consecutive bands of one table row per thread
+
 template <typename TT>
 __global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int item0) {
     const int F = a.nfreq;
+    const int nfb = (F + kSedBands - 1) / kSedBands;  // band groups per row
     const int item = item0 + (int)blockIdx.y;
     if (a.active && !as_const(a.active)[item]) return;
     const int64_t x0 = as_const(xoff)[item], kk = as_const(xoff)[item + 1] - x0;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (parameter, band)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (parameter, band group)
     if (t == 0) a.istatus[item] = 0;
-    if (t >= kk * F) return;
-    const int64_t r = t / F;
-    const int f = (int)(t - r * F);
+    if (t >= kk * nfb) return;
+    const int64_t r = t / nfb;
+    const int fa = (int)(t - r * nfb) * kSedBands;
+    const int fb = fa + kSedBands < F ? fa + kSedBands : F;
     const cptr<ItemDev> it = as_const(a.items) + item;
     const cptr<BandDev> B = as_const(a.band);
     const double x = a.x[x0 + r];
     TT *tab = (TT *)a.tables + it->tab_off * (int64_t)F;
     const int64_t k0 = it->k[0], k1 = it->k[1];
     if (r < k0) {
-        tab[r * F + f] = (TT)exp(x * B->ld[f]);
+        for (int f = fa; f < fb; ++f) tab[r * F + f] = (TT)exp(x * B->ld[f]);
     } else if (r < k0 + k1) {
-        const int64_t kk = r - k0;
-        TT *o = tab + (k0 + 2 * kk) * F;
-        const double x0 = B->hk0d / x;
-        const double xf = B->hk[f] / x;
-        o[2 * f] = (TT)(B->rd[f] * expm1(x0) / expm1(xf));
-        o[2 * f + 1] = (TT)((xf / (-expm1(-xf)) - x0 / (-expm1(-x0))) / x);
+        TT *o = tab + (k0 + 2 * (r - k0)) * F;
+        const double xd = B->hk0d / x;
+        const double e0 = expm1(xd), q0 = xd / (-expm1(-xd));
+        for (int f = fa; f < fb; ++f) {
+            const double xf = B->hk[f] / x;
+            o[2 * f] = (TT)(B->rd[f] * e0 / expm1(xf));
+            o[2 * f + 1] = (TT)((xf / (-expm1(-xf)) - q0) / x);
+        }
     } else {
-        const int64_t kk = r - k0 - k1;
-        tab[(k0 + 2 * k1 + kk) * F + f] = (TT)(exp(x * B->ls[f]) * B->gs[f]);
+        const int64_t ks = r - k0 - k1;
+        for (int f = fa; f < fb; ++f) tab[(k0 + 2 * k1 + ks) * F + f] = (TT)(exp(x * B->ls[f]) * B->gs[f]);
     }
 }
 
@@ -813,6 +819,7 @@ __global__ __launch_bounds__(512) void k_pixel_stage(const EvalArgs a) {
 // a7 (second level): deterministic compensated sums over each cluster's segments
 // ---------------------------------------------------------------------------------------------
 // Grid as for k_sed: x over an item's clusters, y over items.
+template <bool WG, bool WF>
 __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, double *grad,
                                                   double *cluster_f) {
     const int item = item0 + (int)blockIdx.y;
@@ -836,31 +843,34 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     const int b = L.seg_off[j][r], e = L.seg_off[j][r + 1];
     const double *part = a.partials + it.part_off * 4;
     double gs = 0, gc = 0, fs = 0, fc = 0;
-    // segments are scattered in the partials: request kB of them at a time, then add in order
+    // segments are scattered in the partials: kB of them are requested at a time and added in
+    // order, with the next batch's segment indices already in flight
     constexpr int kB = 8;
+    int idx[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) idx[k] = (b + k < e) ? perm[b + k] : 0;
     for (int i0 = b; i0 < e; i0 += kB) {
-        int idx[kB];
         double vg[kB], vf[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) idx[k] = (i0 + k < e) ? perm[i0 + k] : perm[b];
-#pragma unroll
         for (int k = 0; k < kB; ++k) {
-            vg[k] = part[idx[k] * 4 + 1 + j];
-            vf[k] = part[idx[k] * 4];
+            if (WG) vg[k] = part[idx[k] * 4 + 1 + j];
+            if (WF) vf[k] = part[idx[k] * 4];
         }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) idx[k] = (i0 + kB + k < e) ? perm[i0 + kB + k] : 0;
 #pragma unroll
         for (int k = 0; k < kB; ++k)
             if (i0 + k < e) {
-                if (grad) neu_add(gs, gc, vg[k]);
-                if (cluster_f) neu_add(fs, fc, vf[k]);
+                if (WG) neu_add(gs, gc, vg[k]);
+                if (WF) neu_add(fs, fc, vf[k]);
             }
     }
-    if (grad) {
+    if (WG) {
         const double v = gs + gc;
         grad[g] = v;
         if (!isfinite(v)) atomicOr(&a.istatus[item], (int)CS_ITEM_NONFINITE);
     }
-    if (cluster_f) cluster_f[g] = fs + fc;
+    if (WF) cluster_f[g] = fs + fc;
 }
 
 constexpr int kFinThreads = 1024;
@@ -964,7 +974,7 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
 
 cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s) {
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)p->B);
-    const unsigned sblocks = (unsigned)((p->kmax_item * p->F + 255) / 256);
+    const unsigned sblocks = (unsigned)((p->kmax_item * ((p->F + kSedBands - 1) / kSedBands) + 255) / 256);
     for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
         const dim3 grid(sblocks, (unsigned)std::min(kMaxGridY, p->B - b0));
         if (fp32_tables)
@@ -1024,8 +1034,13 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
 
     if (want_grad || cluster_f) {
         for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
-            hipLaunchKernelGGL(k_fin_grad, dim3(kblocks, (unsigned)std::min(kMaxGridY, p->B - b0)), dim3(256), 0, s, a,
-                               xoff_dev, b0, want_grad ? grad : nullptr, cluster_f);
+            const dim3 fgrid(kblocks, (unsigned)std::min(kMaxGridY, p->B - b0));
+            if (want_grad && cluster_f)
+                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
+            else if (want_grad)
+                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
+            else
+                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
             CSI_HIP(hipGetLastError());
         }
     }

@@ -67,7 +67,7 @@ static void carve(cs_problem *p) {
     w.order = take(sizeof(int32_t) * w.p64 * L);
     w.head = take(sizeof(uint64_t) * w.nchunk_max * L);
     w.seg_base = take(sizeof(int32_t) * (w.nchunk_max + 1) * L);
-    w.seg_lab = take(sizeof(int4) * w.p64 * L);
+    w.seg_lab = take(sizeof(int4) * (w.p64 * L + kSegLabPad));
     w.seg_perm = take(sizeof(int32_t) * w.p64 * 3 * L);
     w.seg_off = take(sizeof(int32_t) * (w.kmax[0] + w.kmax[1] + w.kmax[2] + 3) * L);
     w.counts = take(sizeof(int32_t) * 4 * L);

@@ -421,6 +421,7 @@ struct SegRec {  // Cholesky factor of M (inverse diagonal), G_jk, and a positiv
 };
 
 constexpr int kStageSeg = 12;  // segments staged per chunk (more: direct-gather path)
+static_assert(kStageSeg <= kSegLabPad, "twelve label records are read past a chunk's first segment");
 constexpr int kLanesPerSeg = 4;
 
 template <typename TA>
@@ -486,24 +487,78 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
     const gptr<TS> du = dq + (int64_t)F * kChunk;
 
-    // data ring: groups 0 .. kRing-1 requested before anything else
+    // data ring: groups 0 .. kRing-1, requested before anything else, except on the FP32
+    // per-pixel fast path below, which sends it behind its table gathers
     TS rq[kRing][kG], ru[kRing][kG];
+    auto issue_ring = [&]() {
 #pragma unroll
-    for (int r = 0; r < kRing; ++r)
+        for (int r = 0; r < kRing; ++r)
 #pragma unroll
-        for (int j = 0; j < kG; ++j) {
-            const int f0 = r * kG + j;
-            const int f = f0 < F ? f0 : F - 1;
-            rq[r][j] = dq[f * kChunk];
-            ru[r][j] = du[f * kChunk];
-        }
+            for (int j = 0; j < kG; ++j) {
+                const int f0 = r * kG + j;
+                const int f = f0 < F ? f0 : F - 1;
+                rq[r][j] = dq[f * kChunk];
+                ru[r][j] = du[f * kChunk];
+            }
+    };
+    // table offsets of the fast path are 32-bit byte offsets
+    const int64_t trows = kd + 2 * kt + it->k[2];
+    static_assert(kFMax <= 32, "one band per lane of a half-wavefront");
+    const bool fast = sizeof(TA) == 4 && !SHARED && trows * F < (int64_t(1) << 28);
+    if (!fast) issue_ring();
 
     Col4<TA> *cols = (Col4<TA> *)wave_lds;
     TA *c5 = (TA *)(wave_lds + stage_col_bytes<TA>(F));
     SegRec *recs = (SegRec *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
     const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
     const gptr<int> seglab = as_global((const int *)L->seg_lab) + 4 * (int64_t)segbase;
-    if (!SHARED) {
+    if (fast) {
+        // columns (a_d, da_d/dT / a_d, a_s) of every (segment, band): in round r the half-wavefront
+        // h stages segment 2 r + h with lane & 31 = band.  The labels arrive through the scalar
+        // cache (the array is padded, so the records past the chunk's last segment can be read)
+        // and each table's byte offset is formed on the scalar unit as a base plus the second
+        // half's difference; all gathers are issued before the first use.  (FP64 accumulation
+        // keeps the general path: this one's registers would cost it a wavefront per SIMD.)
+        constexpr int kRounds = kStageSeg / 2;
+        const cptr<int> sl = as_const((const int *)L->seg_lab) + 4 * (int64_t)segbase;
+        const int rb = F * (int)sizeof(TA);  // bytes per table row
+        const int kdb = (int)kd * rb, kdtb = (int)(kd + 2 * kt) * rb;
+        const bool hi = lane >= 32;
+        const int f = lane & 31;
+        const int fb = (f < F ? f : F - 1) * (int)sizeof(TA);
+        const int nr = (nseg + 1) >> 1;
+        const char *tb = (const char *)(const TA *)tab;
+        auto at = [&](int e) { return *(gptr<TA>)(tb + (uint32_t)e); };
+        TA pdv[kRounds], btv[kRounds], dtv[kRounds], ssv[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            if (r < nr) {
+                const cptr<int> l0 = sl + 8 * r, l1 = l0 + 4;
+                int bd = l0[0] * rb, bt2 = kdb + l0[1] * 2 * rb, bs = kdtb + l0[2] * rb;
+                // the second half repeats segment 2 r when 2 r + 1 is past the chunk's last one
+                const bool two = 2 * r + 1 < nseg;
+                int dd = two ? l1[0] * rb - bd : 0, dt2 = two ? kdb + l1[1] * 2 * rb - bt2 : 0,
+                    ds = two ? kdtb + l1[2] * rb - bs : 0;
+                // keep the products on the scalar unit (not re-formed per lane after the select)
+                asm volatile("" : "+s"(bd), "+s"(bt2), "+s"(bs), "+s"(dd), "+s"(dt2), "+s"(ds));
+                const int ed = bd + (hi ? dd : 0) + fb;
+                const int et = bt2 + (hi ? dt2 : 0) + 2 * fb;
+                const int es = bs + (hi ? ds : 0) + fb;
+                pdv[r] = at(ed);
+                btv[r] = at(et);
+                dtv[r] = at(et + (int)sizeof(TA));
+                ssv[r] = at(es);
+            }
+        }
+        // the ring goes out behind the gathers: vector-memory loads complete in order, so the
+        // column writes wait only for the gathers while the ring is still in flight
+        issue_ring();
+        const int lbase = (hi ? F : 0) + f;
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r)
+            if (r < nr && f < F && 2 * r + (hi ? 1 : 0) < nseg)
+                cols[2 * r * F + lbase] = Col4<TA>{pdv[r] * btv[r], dtv[r], ssv[r], (TA)0};
+    } else if (!SHARED) {
         // columns (a_d, da_d/dT / a_d, a_s) of every (segment, band), in phases of kPh rounds of
         // the wavefront whose gathers are all issued before their first use
         constexpr int kPh = sizeof(TA) == 4 ? 6 : 3;  // measured best on gfx950 at F = 22
@@ -792,8 +847,16 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     __builtin_amdgcn_wave_barrier();
 }
 
+// Minimum wavefronts per SIMD the register allocation must allow: five in the per-pixel mode with
+// FP32 accumulation (at most 96 VGPRs); the other modes are left to the compiler.
+template <typename TA, bool SHARED>
+constexpr int stage_waves() {
+    return SHARED ? 1 : (sizeof(TA) == 4 ? 5 : 1);
+}
+
 template <typename TS, typename TA, bool GRAD, bool SHARED>
-__global__ __launch_bounds__(512) void k_pixel_stage(const EvalArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<TA, SHARED>()))) void k_pixel_stage(
+    const EvalArgs a) {
     extern __shared__ char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

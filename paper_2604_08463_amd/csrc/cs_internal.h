@@ -14,6 +14,7 @@ namespace csi {
 
 constexpr int kChunk = 64;  // pixels per work unit = lanes of one wavefront
 constexpr int kFMax = 32;   // largest supported band count (register tile)
+constexpr int kSegLabPad = 16;  // records past the end of each seg_lab array (read, never used)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int kNumCu = 256;
 constexpr int kMaxGridY = 65535;  // largest grid dimension y

@@ -71,6 +71,17 @@ def test_fp64_tiny_shapes(nfreq):
     compare(sky, prob, "fp64")
 
 
+@pytest.mark.parametrize("nfreq", [4, 9, 22, 32])
+def test_fp32_bulk_tiny_shapes(nfreq):
+    # the FP32 per-pixel mode stages one band per lane of a half-wavefront
+    sky = skygen.make_tiny(517, nfreq, (5, 3, 4), seed=100 + nfreq, nitems=3, mask_frac=0.1)
+    _log(f"fp32_bulk tiny F={nfreq}")
+    prob = cs.Problem.from_sky(sky, "fp32_bulk")
+    for sh in (0, 1):
+        prob.set_schedule(4, 0, 1, sh)
+        compare(sky, prob, "fp32_bulk")
+
+
 def test_fp64_workload1_all_points():
     sky = skygen.make_config(1)
     _log("fp64 workload 1 (3072 px, 64 points)")
@@ -98,13 +109,15 @@ def test_precisions_and_sharing_workload2(precision, shared):
     _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
 
 
-def test_segment_sharing_ragged_many_segments():
-    # ragged configurations where many chunks hold one-pixel segments
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_segment_sharing_ragged_many_segments(precision):
+    # ragged configurations where many chunks hold one-pixel segments (odd and even segment
+    # counts, and chunks past the staging limit)
     sky = skygen.make_config(4, nitems=3, kmax4=(3000, 500, 1000))
-    prob = cs.Problem.from_sky(sky, "fp64")
+    prob = cs.Problem.from_sky(sky, precision)
     for sh in (1, 0):
         prob.set_schedule(4, 0, 1, sh)
-        compare(sky, prob, "fp64")
+        compare(sky, prob, precision)
 
 
 def test_fp32_input_dtype():

@@ -881,15 +881,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
 // ---------------------------------------------------------------------------------------------
 // a7 (second level): deterministic compensated sums over each cluster's segments
 // ---------------------------------------------------------------------------------------------
-// Grid as for k_sed: x over an item's clusters, y over items.
+// kFinLanes lanes per (item, cluster), on a 1D grid of kblocks workgroups per item.  Lane l of a
+// cluster's group adds the cluster's segments l, l + kFinLanes, ... in order (Neumaier); the
+// group's lane sums are then combined by a fixed butterfly, so the result does not depend on
+// timing.  Workgroups are dealt round-robin to the XCDs, so the grid is renumbered in groups of
+// eight items: the blocks of one item all land on one XCD, whose L2 then holds its partials.
+constexpr int kFinLanes = 8;
+
+__device__ __forceinline__ void neu_combine(double &s, double &c, int off) {
+    const double so = __shfl_xor(s, off, kFinLanes), co = __shfl_xor(c, off, kFinLanes);
+    neu_add(s, c, so);  // symmetric in its two sums, so every lane of the group agrees
+    c += co;
+}
+
 template <bool WG, bool WF>
-__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, double *grad,
-                                                  double *cluster_f) {
-    const int item = item0 + (int)blockIdx.y;
+__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, int nitems,
+                                                  int kblocks, double *grad, double *cluster_f) {
+    const int64_t lin = blockIdx.x;
+    const int64_t grp = lin / (kNumXcd * (int64_t)kblocks);
+    const int64_t rem = lin - grp * kNumXcd * (int64_t)kblocks;
+    const int ng = (int)min((int64_t)kNumXcd, (int64_t)nitems - grp * kNumXcd);  // items in this group
+    const int item = item0 + (int)(grp * kNumXcd + rem % ng);
+    const int64_t xb = rem / ng;
     if (a.active && !as_const(a.active)[item]) return;
     const int64_t x0 = as_const(xoff)[item];
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= as_const(xoff)[item + 1] - x0) return;
+    const int sub = threadIdx.x % kFinLanes;
+    int64_t r = xb * (blockDim.x / kFinLanes) + threadIdx.x / kFinLanes;
+    if (r >= as_const(xoff)[item + 1] - x0) return;  // whole groups leave together
     const int64_t g = x0 + r;
     const ItemDev &it = a.items[item];
     const LayoutDev &L = a.layouts[it.layout];
@@ -906,13 +924,17 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     const int b = L.seg_off[j][r], e = L.seg_off[j][r + 1];
     const double *part = a.partials + it.part_off * 4;
     double gs = 0, gc = 0, fs = 0, fc = 0;
-    // segments are scattered in the partials: kB of them are requested at a time and added in
-    // order, with the next batch's segment indices already in flight
-    constexpr int kB = 8;
+    // segments are scattered in the partials: kB of the lane's segments are requested at a time,
+    // with the next batch's segment indices already in flight
+    constexpr int kB = 4;
+    constexpr int kStep = kB * kFinLanes;
     int idx[kB];
 #pragma unroll
-    for (int k = 0; k < kB; ++k) idx[k] = (b + k < e) ? perm[b + k] : 0;
-    for (int i0 = b; i0 < e; i0 += kB) {
+    for (int k = 0; k < kB; ++k) {
+        const int i = b + sub + k * kFinLanes;
+        idx[k] = i < e ? perm[i] : 0;
+    }
+    for (int i0 = b + sub; i0 < e; i0 += kStep) {
         double vg[kB], vf[kB];
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
@@ -920,14 +942,23 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
             if (WF) vf[k] = part[idx[k] * 4];
         }
 #pragma unroll
-        for (int k = 0; k < kB; ++k) idx[k] = (i0 + kB + k < e) ? perm[i0 + kB + k] : 0;
+        for (int k = 0; k < kB; ++k) {
+            const int i = i0 + kStep + k * kFinLanes;
+            idx[k] = i < e ? perm[i] : 0;
+        }
 #pragma unroll
         for (int k = 0; k < kB; ++k)
-            if (i0 + k < e) {
+            if (i0 + k * kFinLanes < e) {
                 if (WG) neu_add(gs, gc, vg[k]);
                 if (WF) neu_add(fs, fc, vf[k]);
             }
     }
+#pragma unroll
+    for (int off = kFinLanes / 2; off > 0; off >>= 1) {
+        if (WG) neu_combine(gs, gc, off);
+        if (WF) neu_combine(fs, fc, off);
+    }
+    if (sub != 0) return;
     if (WG) {
         const double v = gs + gc;
         grad[g] = v;
@@ -1055,7 +1086,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     EvalArgs a = make_eval_args(p, x, active);
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
     const bool t32 = (mode == CS_FP32_BULK);
-    const unsigned kblocks = (unsigned)((p->kmax_item + 255) / 256);
+    const unsigned kblocks = (unsigned)((p->kmax_item * kFinLanes + 255) / 256);
 
     const cs_status sst = launch_sed(p, a, t32, s);
     if (sst != CS_OK) return sst;
@@ -1096,14 +1127,21 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 
     if (want_grad || cluster_f) {
-        for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
-            const dim3 fgrid(kblocks, (unsigned)std::min(kMaxGridY, p->B - b0));
+        // items per launch: the 1D grid stays below 2^31 workgroups
+        const int per = (int)std::min<int64_t>(p->B, std::max<int64_t>(1, ((int64_t(1) << 31) - 1) / kblocks));
+        for (int b0 = 0; b0 < p->B; b0 += per) {
+            const int nb = std::min(per, p->B - b0);
+            const dim3 fgrid((unsigned)((int64_t)kblocks * nb));
+            const int kb = (int)kblocks;
             if (want_grad && cluster_f)
-                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
+                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                                   cluster_f);
             else if (want_grad)
-                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
+                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                                   cluster_f);
             else
-                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, grad, cluster_f);
+                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                                   cluster_f);
             CSI_HIP(hipGetLastError());
         }
     }

@@ -4,7 +4,9 @@
 // Sec. 2.2-2.3).  The evaluation kernels want the pixels of one item ordered so that every
 // 64-pixel chunk (one wavefront) holds few runs of constant (l_d, l_T, l_s), and every data
 // byte is streamed once, coalesced.  Everything here runs on the device:
-//   1. keys  = (l_d, l_T, l_s, p) packed in 64 bits (unique), invalid labels flagged;
+//   1. keys  = (l_T, l_d, l_s, p) packed in 64 bits (unique), invalid labels flagged: the
+//      segments of one T_d patch, and those of one beta_d patch inside it, are then
+//      neighbours in the partials that the per-patch sums gather;
 //   2. bitonic sort of the keys (unique keys => the order is deterministic);
 //   3. chunk heads (ballot of run starts), per-chunk segment counts, segment triples;
 //   4. per labelling, a bitonic sort of (label, segment) -> segment CSR;
@@ -113,7 +115,7 @@ struct KeyBits {
     int bd, bt, bs, bp;
 };
 
-// 1. keys = (l_d, l_T, l_s, p); invalid labels set the error flag; excluded pixels sort last.
+// 1. keys = (l_T, l_d, l_s, p); invalid labels set the error flag; excluded pixels sort last.
 __global__ __launch_bounds__(256) void k_make_keys(const LayoutDev *lays, int32_t npix, int64_t np2, KeyBits kb) {
     const LayoutDev L = lays[blockIdx.y];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(256) void k_make_keys(const LayoutDev *lays, int32_
         const int nexcl = (a == -1) + (b == -1) + (c == -1);
         const bool inrange = a >= 0 && a < L.k[0] && b >= 0 && b < L.k[1] && c >= 0 && c < L.k[2];
         if (nexcl == 0 && inrange) {
-            key = ((uint64_t)a << (kb.bt + kb.bs + kb.bp)) | ((uint64_t)b << (kb.bs + kb.bp)) |
+            key = ((uint64_t)b << (kb.bd + kb.bs + kb.bp)) | ((uint64_t)a << (kb.bs + kb.bp)) |
                   ((uint64_t)c << kb.bp) | (uint64_t)i;
         } else if (nexcl != 3) {
             atomicOr(&L.counts[2], 1);
@@ -194,8 +196,8 @@ __global__ __launch_bounds__(64) void k_seg_lab(const LayoutDev *lays, KeyBits k
     const uint64_t key = L.keys[slot];
     const int seg = L.seg_base[chunk] + __popcll(mask & ((1ull << lane) - 1ull));
     int4 v;
-    v.x = (int)((key >> (kb.bt + kb.bs + kb.bp)) & ((1ull << kb.bd) - 1ull));
-    v.y = (int)((key >> (kb.bs + kb.bp)) & ((1ull << kb.bt) - 1ull));
+    v.y = (int)((key >> (kb.bd + kb.bs + kb.bp)) & ((1ull << kb.bt) - 1ull));
+    v.x = (int)((key >> (kb.bs + kb.bp)) & ((1ull << kb.bd) - 1ull));
     v.z = (int)((key >> kb.bp) & ((1ull << kb.bs) - 1ull));
     v.w = (int)slot;
     L.seg_lab[seg] = v;

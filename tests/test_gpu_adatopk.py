@@ -93,9 +93,14 @@ def test_adatopk_workload3_items_reach_lbfgs_optimum():
     sky = skygen.make_config(3, nitems=8, device="cuda")
     lo, hi = sky.bounds_packed()
     prob = cs.Problem.from_sky(sky, "fp64")
-    x_l = prob.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts())["x"].cpu().numpy()
+    rl = prob.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts())
+    x_l = rl["x"].cpu().numpy()
     r = _run(prob, lo, hi, sky.x_packed(), max_iter=4000)
     _log(f"workload 3: status {r['status']} iters {r['iters']} evals {r['nevals']}")
+    _log(f"  F adatopk {np.array2string(np.asarray(r['f']), precision=10)}")
+    _log(f"  F lbfgs   {np.array2string(rl['f'].cpu().numpy(), precision=10)}")
+    _log(f"  x adatopk {np.array2string(np.asarray(r['x']), precision=6)}")
+    _log(f"  x lbfgs   {np.array2string(x_l, precision=6)}")
     assert np.all(r["status"] & cs.CONVERGED)
     assert np.all(np.abs(r["x"] - x_l) <= 1e-4 * np.maximum(1.0, np.abs(x_l)))
 

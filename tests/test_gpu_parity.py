@@ -49,9 +49,9 @@ def test_segments_bit_exact(case):
             rp, ro = oracle.segments(lab[j], int(sky.nclusters[b, j]))
             assert np.array_equal(perm.cpu().numpy(), rp)
             assert np.array_equal(off.cpu().numpy(), ro)
-        # segments = runs of constant (l_d, l_T, l_s) in (l_d, l_T, l_s, p) order cut every 64 pixels
+        # segments = runs of constant (l_d, l_T, l_s) in (l_T, l_d, l_s, p) order cut every 64 pixels
         inc = np.flatnonzero(lab[0] >= 0)
-        order = inc[np.lexsort((inc, lab[2, inc], lab[1, inc], lab[0, inc]))]
+        order = inc[np.lexsort((inc, lab[2, inc], lab[0, inc], lab[1, inc]))]
         trip = lab[:, order].T
         heads = np.ones(len(order), dtype=bool)
         heads[1:] = np.any(trip[1:] != trip[:-1], axis=1)

@@ -107,7 +107,7 @@ cs_status cs_problem_workspace_bytes(const cs_problem *prob, size_t *bytes);
 
 /* Segment preparation, once per clustering (paper Sec. 2.2-2.3: patches are disjoint pixel
  * sets, one patching per parameter).  On the device: validates the labels, orders the
- * included pixels by (l_d, l_T, l_s, p), cuts the order into 64-pixel chunks and constant-
+ * included pixels by (l_T, l_d, l_s, p), cuts the order into 64-pixel chunks and constant-
  * label runs (segments), builds each labelling's segment CSR, and packs d (and per-pixel
  * N^-1) into the workspace in that order and in the working precision.  Synchronises the
  * stream.  Returns CS_E_LABEL on a bad label.  After it returns, d / ninv_pixel / labels are

@@ -469,8 +469,9 @@ template <typename TS, typename TA, bool GRAD, bool SHARED>
 __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, const int chunk, const int lane,
                                             char *wave_lds) {
     // groups of kG bands in flight per lane: the segment-shared band loop is short (12 FMAs per
-    // band), so it looks further ahead (measured on gfx950: 8 groups for it, 4 for per-pixel)
-    constexpr int kRing = SHARED ? 8 : 4;
+    // band), so it looks further ahead (measured on gfx950: 8 groups for it; 6 for per-pixel with
+    // FP32 accumulation, 4 with FP64, whose registers would otherwise cost it a wavefront)
+    constexpr int kRing = SHARED ? 8 : (sizeof(TA) == 4 ? 6 : 4);
     constexpr int kG = 2;
     const cptr<BandDev> B = as_const(a.band);
     const int F = a.nfreq;

@@ -882,12 +882,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
 // ---------------------------------------------------------------------------------------------
 // a7 (second level): deterministic compensated sums over each cluster's segments
 // ---------------------------------------------------------------------------------------------
-// kFinLanes lanes per (item, cluster), on a 1D grid of kblocks workgroups per item.  Lane l of a
-// cluster's group adds the cluster's segments l, l + kFinLanes, ... in order (Neumaier); the
-// group's lane sums are then combined by a fixed butterfly, so the result does not depend on
-// timing.  Workgroups are dealt round-robin to the XCDs, so the grid is renumbered in groups of
-// eight items: the blocks of one item all land on one XCD, whose L2 then holds its partials.
-constexpr int kFinLanes = 8;
+// One launch for the second level of a7.  Its first nitems * kFSlices workgroups each add one
+// slice of an item's segment values f (Neumaier, then a fixed tree over the workgroup) into
+// fpart; k_fin_f folds the slices in order.  The remaining workgroups hold kFinLanes lanes per
+// (item, cluster): lane l of a cluster's group adds the cluster's segments l, l + kFinLanes, ...
+// in order, and the group's lane sums are combined by a fixed butterfly, so no result depends on
+// timing.  Workgroups are dealt round-robin to the XCDs, so the cluster part of the grid is
+// renumbered in groups of eight items: the blocks of one item all land on one XCD, whose L2 then
+// holds its partials.
+constexpr int kFinLanes = 4;
+constexpr int kFinBlock = 256;
 
 __device__ __forceinline__ void neu_combine(double &s, double &c, int off) {
     const double so = __shfl_xor(s, off, kFinLanes), co = __shfl_xor(c, off, kFinLanes);
@@ -895,10 +899,56 @@ __device__ __forceinline__ void neu_combine(double &s, double &c, int off) {
     c += co;
 }
 
+__device__ __forceinline__ void f_slice(const EvalArgs &a, const int item, const int sl) {
+    const ItemDev &it = a.items[item];
+    const LayoutDev &L = a.layouts[it.layout];
+    const int64_t n = L.nseg;
+    const int64_t b = sl * n / kFSlices, e = (sl + 1) * n / kFSlices;
+    const double *part = a.partials + it.part_off * 4;
+    double s = 0, c = 0;
+    constexpr int kU = 4;
+    for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += kU * kFinBlock) {
+        double v[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const int64_t i = i0 + (int64_t)k * kFinBlock;
+            v[k] = i < e ? part[i * 4] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kU; ++k) neu_add(s, c, v[k]);
+    }
+    __shared__ double ss[kFinBlock], sc[kFinBlock];
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = kFinBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            double s1 = ss[threadIdx.x], c1 = sc[threadIdx.x];
+            neu_add(s1, c1, ss[threadIdx.x + st]);
+            ss[threadIdx.x] = s1;
+            sc[threadIdx.x] = c1 + sc[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *o = a.fpart + ((int64_t)item * kFSlices + sl) * 2;
+        o[0] = ss[0];
+        o[1] = sc[0];
+    }
+}
+
 template <bool WG, bool WF>
-__global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, int nitems,
-                                                  int kblocks, double *grad, double *cluster_f) {
-    const int64_t lin = blockIdx.x;
+__global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, int nitems,
+                                                        int kblocks, double *grad, double *cluster_f) {
+    const int64_t nf = (int64_t)nitems * kFSlices;
+    if ((int64_t)blockIdx.x < nf) {  // F slices
+        const int item = item0 + (int)(blockIdx.x / kFSlices);
+        if (a.active && !as_const(a.active)[item]) return;
+        f_slice(a, item, (int)(blockIdx.x % kFSlices));
+        return;
+    }
+    if (!WG && !WF) return;
+    const int64_t lin = blockIdx.x - nf;
     const int64_t grp = lin / (kNumXcd * (int64_t)kblocks);
     const int64_t rem = lin - grp * kNumXcd * (int64_t)kblocks;
     const int ng = (int)min((int64_t)kNumXcd, (int64_t)nitems - grp * kNumXcd);  // items in this group
@@ -907,7 +957,7 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     if (a.active && !as_const(a.active)[item]) return;
     const int64_t x0 = as_const(xoff)[item];
     const int sub = threadIdx.x % kFinLanes;
-    int64_t r = xb * (blockDim.x / kFinLanes) + threadIdx.x / kFinLanes;
+    int64_t r = xb * (kFinBlock / kFinLanes) + threadIdx.x / kFinLanes;
     if (r >= as_const(xoff)[item + 1] - x0) return;  // whole groups leave together
     const int64_t g = x0 + r;
     const ItemDev &it = a.items[item];
@@ -968,49 +1018,28 @@ __global__ __launch_bounds__(256) void k_fin_grad(const EvalArgs a, const int64_
     if (WF) cluster_f[g] = fs + fc;
 }
 
-constexpr int kFinThreads = 1024;
-
-__global__ __launch_bounds__(kFinThreads) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
-    const int item = blockIdx.x;
+// F of each item: its slices folded in order, then the status word (after the cluster sums,
+// which flag a non-finite gradient).  One thread per item.
+__global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= a.nitems) return;
     if (a.active && !a.active[item]) return;
-    const ItemDev &it = a.items[item];
-    const LayoutDev &L = a.layouts[it.layout];
-    const int n = L.nseg;
-    const double *part = a.partials + it.part_off * 4;
+    const double *fp = a.fpart + (int64_t)item * kFSlices * 2;
     double s = 0, c = 0;
-    constexpr int kU = 4;
-    for (int i0 = threadIdx.x; i0 < n; i0 += kU * kFinThreads) {
-        double v[kU];
 #pragma unroll
-        for (int k = 0; k < kU; ++k) {
-            const int i = i0 + k * kFinThreads;
-            v[k] = i < n ? part[(int64_t)i * 4] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < kU; ++k) neu_add(s, c, v[k]);
+    for (int sl = 0; sl < kFSlices; ++sl) {
+        neu_add(s, c, fp[2 * sl]);
+        c += fp[2 * sl + 1];
     }
-    __shared__ double ss[kFinThreads], sc[kFinThreads];
-    ss[threadIdx.x] = s;
-    sc[threadIdx.x] = c;
-    __syncthreads();
-    for (int st = kFinThreads / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            double s1 = ss[threadIdx.x], c1 = sc[threadIdx.x];
-            neu_add(s1, c1, ss[threadIdx.x + st]);
-            ss[threadIdx.x] = s1;
-            sc[threadIdx.x] = c1 + sc[threadIdx.x + st];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        int st = a.istatus[item];
-        double v = ss[0] + sc[0];
-        if (st & CS_ITEM_NOT_PD) v = __builtin_nan("");
-        else if (!isfinite(v)) st |= CS_ITEM_NONFINITE;
-        neg2logl[item] = v;
-        if (status) status[item] = st;
-        a.istatus[item] = st;
-    }
+    int st = a.istatus[item];
+    double v = s + c;
+    if (st & CS_ITEM_NOT_PD)
+        v = __builtin_nan("");
+    else if (!isfinite(v))
+        st |= CS_ITEM_NONFINITE;
+    neg2logl[item] = v;
+    if (status) status[item] = st;
+    a.istatus[item] = st;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1058,6 +1087,7 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
     a.band = (const BandDev *)(p->wsp + w.band);
     a.partials = (double *)(p->wsp + w.partials);
     a.istatus = (int32_t *)(p->wsp + w.istatus);
+    a.fpart = (double *)(p->wsp + w.fpart);
     a.active = active;
     a.x = x;
     a.nitems = p->B;
@@ -1087,7 +1117,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     EvalArgs a = make_eval_args(p, x, active);
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
     const bool t32 = (mode == CS_FP32_BULK);
-    const unsigned kblocks = (unsigned)((p->kmax_item * kFinLanes + 255) / 256);
+    const unsigned kblocks = (unsigned)((p->kmax_item * kFinLanes + kFinBlock - 1) / kFinBlock);
 
     const cs_status sst = launch_sed(p, a, t32, s);
     if (sst != CS_OK) return sst;
@@ -1127,26 +1157,30 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 
-    if (want_grad || cluster_f) {
+    {
         // items per launch: the 1D grid stays below 2^31 workgroups
-        const int per = (int)std::min<int64_t>(p->B, std::max<int64_t>(1, ((int64_t(1) << 31) - 1) / kblocks));
+        const int64_t per_item = (int64_t)kFSlices + ((want_grad || cluster_f) ? (int64_t)kblocks : 0);
+        const int per = (int)std::min<int64_t>(p->B, std::max<int64_t>(1, ((int64_t(1) << 31) - 1) / per_item));
         for (int b0 = 0; b0 < p->B; b0 += per) {
             const int nb = std::min(per, p->B - b0);
-            const dim3 fgrid((unsigned)((int64_t)kblocks * nb));
+            const dim3 fgrid((unsigned)(per_item * nb));
             const int kb = (int)kblocks;
             if (want_grad && cluster_f)
-                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
                                    cluster_f);
             else if (want_grad)
-                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                                   cluster_f);
+            else if (cluster_f)
+                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
                                    cluster_f);
             else
-                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(256), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<false, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
                                    cluster_f);
             CSI_HIP(hipGetLastError());
         }
     }
-    hipLaunchKernelGGL(k_fin_f, dim3(p->B), dim3(kFinThreads), 0, s, a, neg2logl, status);
+    hipLaunchKernelGGL(k_fin_f, dim3((unsigned)((p->B + 255) / 256)), dim3(256), 0, s, a, neg2logl, status);
     CSI_HIP(hipGetLastError());
     return CS_OK;
 }

@@ -286,6 +286,30 @@ int orc_likelihood_grad(const orc_problem *pr, const double *x, double *neg2logl
     return status;
 }
 
+/*
+ * Scale of each cluster's gradient sum: gabs[k] = sum over the cluster's pixels of |dF_p/dtheta_k|
+ * (packed like grad).  The gradient of a cluster is a sum of per-pixel terms of both signs that
+ * nearly cancel at an optimum, so its rounding error is bounded relative to this sum, not to the
+ * gradient itself: the per-cluster tolerance is stated against it.  Plain sums in ascending pixel
+ * order.  Returns status bits (>= 0) or a negative error code.
+ */
+int orc_grad_abs(const orc_problem *pr, const double *x, double *gabs) {
+    int rc = orc_check_labels(pr);
+    if (rc) return rc;
+    const int64_t P = pr->npix;
+    const int K = pr->nclusters[0] + pr->nclusters[1] + pr->nclusters[2];
+    const int off[3] = {0, pr->nclusters[0], pr->nclusters[0] + pr->nclusters[1]};
+    for (int k = 0; k < K; ++k) gabs[k] = 0.0;
+    int status = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (pr->labels[p] < 0) continue;
+        double f, g[3];
+        status |= orc_pixel(pr, x, (int32_t)p, NULL, NULL, NULL, NULL, &f, g);
+        for (int j = 0; j < 3; ++j) gabs[off[j] + pr->labels[j * P + p]] += fabs(g[j]);
+    }
+    return status;
+}
+
 /* d^T N^-1 d over the included pixels (the data term of the joint chi^2, Sec. 2.1 eq. nll_joint) */
 double orc_data_chi2(const orc_problem *pr) {
     const int F = pr->nfreq;

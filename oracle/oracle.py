@@ -59,6 +59,7 @@ def lib():
         L.orc_check_labels.argtypes = [P(_Problem)]
         L.orc_pixel.argtypes = [P(_Problem), dp, C.c_int32, dp, dp, dp, dp, dp, dp]
         L.orc_likelihood_grad.argtypes = [P(_Problem), dp, dp, dp, dp]
+        L.orc_grad_abs.argtypes = [P(_Problem), dp, dp]
         L.orc_component_maps.argtypes = [P(_Problem), dp, dp, dp]
         L.orc_data_chi2.argtypes = [P(_Problem)]
         L.orc_data_chi2.restype = C.c_double
@@ -121,6 +122,17 @@ class Problem:
         if st < 0:
             raise ValueError(f"oracle error {st}")
         return float(f[0]), g, cf, st
+
+    def grad_abs(self, x):
+        """Per cluster (packed like the gradient) the sum over its pixels of |dF_p/dtheta|: the
+        scale against which a cluster's gradient error is bounded."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.size == self.K
+        ga = np.zeros(self.K)
+        st = lib().orc_grad_abs(C.byref(self._s), _dp(x), _dp(ga))
+        if st < 0:
+            raise ValueError(f"oracle error {st}")
+        return ga
 
     def pixel(self, x, p: int):
         """Per-pixel details: dict(M [2,3,3], b [2,3], s [2,3], r [2,F], f, g [3], status)."""

@@ -82,6 +82,31 @@ def test_fp32_bulk_tiny_shapes(nfreq):
         compare(sky, prob, "fp32_bulk")
 
 
+def test_fp64_gradient_per_cluster_condition_aware():
+    # near an optimum a cluster's gradient is a sum of nearly cancelling per-pixel terms, so its
+    # error is bounded per cluster against sum_{p in k} |dF_p/dtheta|: at the start point and at
+    # the batched L-BFGS optimum, |g_k - g_k(oracle)| <= 1e-9 of that sum
+    sky = skygen.make_config(2, npix=8000, nitems=2, k=(200, 20, 60))
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = prob.cs_optimize_batch(lo, hi, sky.x_packed())
+    xs = r["x"].cpu().numpy()
+    off = sky.param_offsets()
+    x_opt = [xs[off[b]:off[b + 1]] for b in range(sky.nitems)]
+    for name, x in (("start", sky.x), ("optimum", x_opt)):
+        _, g, _, st = gpu_eval(prob, sky, x, cluster=False)
+        for b in range(sky.nitems):
+            po = oracle.Problem.from_sky(sky, b)
+            _, go, _, so = po.likelihood_grad(x[b])
+            ga = po.grad_abs(x[b])
+            gb = g[off[b]:off[b + 1]]
+            assert st[b] == so
+            err = np.abs(gb - go)
+            _log(f"  {name} item {b}: max |dg|/sum|g_p| {np.max(err / np.maximum(ga, 1e-300)):.2e}, "
+                 f"max |g|/sum|g_p| {np.max(np.abs(go) / np.maximum(ga, 1e-300)):.2e}")
+            assert np.all(err <= 1e-9 * ga)
+
+
 def test_fp64_workload1_all_points():
     sky = skygen.make_config(1)
     _log("fp64 workload 1 (3072 px, 64 points)")

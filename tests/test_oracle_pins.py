@@ -277,6 +277,33 @@ def test_gradient_central_differences():
         assert abs(fd - g[i]) <= 1e-5 * max(abs(g[i]), 1e-2 * np.max(np.abs(g)))
 
 
+def test_gradient_abs_scale_of_clusters():
+    # the per-cluster scale sum_p |dF_p/dtheta| of the condition-aware gradient tolerance: it is
+    # the sum of the per-pixel gradients' magnitudes (per-pixel gradients summed, signed, give the
+    # complex-step-pinned gradient), bounds |grad| from above, and equals it for one-pixel clusters
+    sky = skygen.make_tiny(40, 15, (3, 2, 40), seed=8)
+    pr = O.Problem.from_sky(sky)
+    x = sky.x[0]
+    _, g, _, _ = pr.likelihood_grad(x)
+    ga = pr.grad_abs(x)
+    lab = sky.item_labels(0)
+    K = sky.nclusters[0]
+    off = [0, K[0], K[0] + K[1]]
+    brute = np.zeros_like(ga)
+    signed = np.zeros_like(ga)
+    for p in range(sky.npix):
+        gp = pr.pixel(x, p)["g"]
+        for j in range(3):
+            brute[off[j] + lab[j, p]] += abs(gp[j])
+            signed[off[j] + lab[j, p]] += gp[j]
+    assert np.allclose(signed, g, rtol=1e-12, atol=0)
+    assert np.allclose(ga, brute, rtol=1e-14, atol=0)
+    assert np.all(np.abs(g) <= ga * (1 + 1e-14))
+    single = off[2] + np.arange(K[2])  # 40 beta_s clusters of one pixel each
+    assert np.array_equal(np.bincount(lab[2], minlength=K[2]), np.ones(K[2], dtype=int))
+    assert np.allclose(ga[single], np.abs(g[single]), rtol=1e-15, atol=0)
+
+
 # --------------------------------------------------------------------------------------------
 # invariants of the spectral likelihood
 # --------------------------------------------------------------------------------------------

@@ -96,6 +96,12 @@ static void fill_band(const cs_problem *p, BandDev &b) {
         for (int s = 0; s < 2; ++s) b.wf[s][f] = (float)b.w[s][f];
         b.ldf[f] = (float)b.ld[f];
         b.lsf[f] = (float)b.ls[f];
+        b.bcd[f][0] = b.w[0][f];
+        b.bcd[f][1] = b.ld[f];
+        b.bcd[f][2] = b.ls[f];
+        b.bcf[f][0] = b.wf[0][f];
+        b.bcf[f][1] = b.ldf[f];
+        b.bcf[f][2] = b.lsf[f];
     }
     b.hk0d = kHOverK * p->nu0d;
     for (int s = 0; s < 2; ++s) {

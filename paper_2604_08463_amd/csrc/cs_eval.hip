@@ -414,11 +414,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
 //     (12 FMAs per band) and reads its segment's factor.
 // Chunks with more than kStageSeg segments take the direct-gather per-pixel path.
 // ---------------------------------------------------------------------------------------------
-struct SegRec {  // Cholesky factor of M (inverse diagonal), G_jk, and a positive-definite flag
-    double i00, l10, l20, i11, l21, i22;
-    double g01, g02, g03, g11, g12, g13, g21, g22, g23;
-    double ok;
-};
+// Per segment: the Cholesky factor of M (inverse diagonal), G_jk and a positive-definite flag,
+// held field-major in the slice (double [kRecFields][kStageSeg]): the lanes of different segments
+// then write and read consecutive words, free of LDS bank conflicts.
+enum RecField { kI00, kL10, kL20, kI11, kL21, kI22, kG01, kG02, kG03, kG11, kG12, kG13, kG21, kG22, kG23, kOk,
+                kRecFields };
 
 constexpr int kStageSeg = 12;  // segments staged per chunk (more: direct-gather path)
 static_assert(kStageSeg <= kSegLabPad, "twelve label records are read past a chunk's first segment");
@@ -430,7 +430,7 @@ struct alignas(4 * sizeof(TA)) Col4 {
 };
 
 // LDS slice of one wavefront: Col4 [kStageSeg][F]; the segment-shared mode adds TA [kStageSeg][F]
-// (16-byte padded) and SegRec [kStageSeg]
+// (16-byte padded) and double [kRecFields][kStageSeg]
 template <typename TA>
 __host__ __device__ constexpr size_t stage_col_bytes(int F) {
     return (size_t)kStageSeg * (size_t)F * sizeof(Col4<TA>);
@@ -441,7 +441,7 @@ __host__ __device__ constexpr size_t stage_c5_bytes(int F) {
 }
 template <typename TA, bool SHARED>
 __host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
-    return SHARED ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kStageSeg * sizeof(SegRec)
+    return SHARED ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
                   : stage_col_bytes<TA>(F);
 }
 
@@ -510,7 +510,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
 
     Col4<TA> *cols = (Col4<TA> *)wave_lds;
     TA *c5 = (TA *)(wave_lds + stage_col_bytes<TA>(F));
-    SegRec *recs = (SegRec *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
+    double *recs = (double *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
     const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
     const gptr<int> seglab = as_global((const int *)L->seg_lab) + 4 * (int64_t)segbase;
     if (fast) {
@@ -596,8 +596,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     } else {
         // coefficients (w a_d, w a_s, w a_d ln(nu/nu0d), w da_d/dT, w a_s ln(nu/nu0s)) of every
         // (segment, band), and the segment's M and G sums: lane = 4 segment + part, bands
-        // part, part + 4, ...; every gather is issued before the first use
-        // phases of kPh bands per lane, every gather of a phase issued before its first use
+        // part, part + 4, ...; phases of kPh bands per lane, every gather of a phase issued before
+        // its first use
         constexpr int kPh = sizeof(TA) == 4 ? 4 : 2;
         const int sg = lane / kLanesPerSeg, part = lane % kLanesPerSeg;
         const bool act = sg < nseg;
@@ -606,7 +606,9 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const gptr<TA> pd = tab + (int64_t)ld * F;
         const gptr<TA> bt = tab + (kd + 2 * (int64_t)lt) * F;
         const gptr<TA> ss = tab + (kd + 2 * kt + ls) * F;
-        const gptr<BandDev> Bg = as_global((const BandDev *)a.band);
+        const BandDev *Bp = a.band;
+        const gptr<TA> bc = as_global(sizeof(TA) == 8 ? (const TA *)(const void *)&Bp->bcd[0][0]
+                                                      : (const TA *)(const void *)&Bp->bcf[0][0]);
         WAcc<TA> P = WAcc<TA>{};
         for (int f0 = 0; f0 < F; f0 += kLanesPerSeg * kPh) {
             TA pdv[kPh], btv[kPh], dtv[kPh], ssv[kPh], wv[kPh], ldv[kPh], lsv[kPh];
@@ -614,15 +616,10 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             for (int i = 0; i < kPh; ++i) {
                 const int fr = f0 + part + kLanesPerSeg * i;
                 const int f = fr < F ? fr : F - 1;
-                if constexpr (sizeof(TA) == 8) {
-                    wv[i] = Bg->w[0][f];
-                    ldv[i] = Bg->ld[f];
-                    lsv[i] = Bg->ls[f];
-                } else {
-                    wv[i] = Bg->wf[0][f];
-                    ldv[i] = Bg->ldf[f];
-                    lsv[i] = Bg->lsf[f];
-                }
+                const gptr<TA> c = bc + 4 * f;  // (w, ln(nu/nu0d), ln(nu/nu0s), 0)
+                wv[i] = c[0];
+                ldv[i] = c[1];
+                lsv[i] = c[2];
                 pdv[i] = pd[f];
                 btv[i] = bt[2 * f];
                 dtv[i] = bt[2 * f + 1];
@@ -677,26 +674,30 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         if (part == 0 && sg < nseg) {
             const double m00 = (double)Band<TA>::wsum(B, 0);
             const double m01 = P.m01, m02 = P.m02, m11 = P.m11, m12 = P.m12, m22 = P.m22;
-            SegRec r;
-            r.i00 = 1.0 / sqrt(m00);
-            r.l10 = m01 * r.i00;
-            r.l20 = m02 * r.i00;
-            const double p1 = m11 - r.l10 * r.l10;
-            r.i11 = 1.0 / sqrt(p1);
-            r.l21 = (m12 - r.l20 * r.l10) * r.i11;
-            const double p2 = m22 - r.l20 * r.l20 - r.l21 * r.l21;
-            r.i22 = 1.0 / sqrt(p2);
-            r.ok = pd_pivots<TA>(m00, m11, m22, p1, p2) ? 1.0 : 0.0;
-            r.g01 = P.g01;
-            r.g02 = P.g02;
-            r.g03 = P.g03;
-            r.g11 = P.g11;
-            r.g12 = P.g12;
-            r.g13 = P.g13;
-            r.g21 = P.g21;
-            r.g22 = P.g22;
-            r.g23 = P.g23;
-            recs[sg] = r;
+            const double i00 = 1.0 / sqrt(m00);
+            const double l10 = m01 * i00, l20 = m02 * i00;
+            const double p1 = m11 - l10 * l10;
+            const double i11 = 1.0 / sqrt(p1);
+            const double l21 = (m12 - l20 * l10) * i11;
+            const double p2 = m22 - l20 * l20 - l21 * l21;
+            const double i22 = 1.0 / sqrt(p2);
+            double *r = recs + sg;
+            r[kI00 * kStageSeg] = i00;
+            r[kL10 * kStageSeg] = l10;
+            r[kL20 * kStageSeg] = l20;
+            r[kI11 * kStageSeg] = i11;
+            r[kL21 * kStageSeg] = l21;
+            r[kI22 * kStageSeg] = i22;
+            r[kOk * kStageSeg] = pd_pivots<TA>(m00, m11, m22, p1, p2) ? 1.0 : 0.0;
+            r[kG01 * kStageSeg] = P.g01;
+            r[kG02 * kStageSeg] = P.g02;
+            r[kG03 * kStageSeg] = P.g03;
+            r[kG11 * kStageSeg] = P.g11;
+            r[kG12 * kStageSeg] = P.g12;
+            r[kG13 * kStageSeg] = P.g13;
+            r[kG21 * kStageSeg] = P.g21;
+            r[kG22 * kStageSeg] = P.g22;
+            r[kG23 * kStageSeg] = P.g23;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -787,17 +788,17 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     double i00, l10, l20, i11, l21, i22, G[9];
     bool ok;
     if (SHARED) {
-        const SegRec &R = recs[segl];
-        i00 = R.i00;
-        l10 = R.l10;
-        l20 = R.l20;
-        i11 = R.i11;
-        l21 = R.l21;
-        i22 = R.i22;
-        G[0] = R.g01; G[1] = R.g02; G[2] = R.g03;
-        G[3] = R.g11; G[4] = R.g12; G[5] = R.g13;
-        G[6] = R.g21; G[7] = R.g22; G[8] = R.g23;
-        ok = R.ok != 0.0;
+        const double *R = recs + segl;
+        i00 = R[kI00 * kStageSeg];
+        l10 = R[kL10 * kStageSeg];
+        l20 = R[kL20 * kStageSeg];
+        i11 = R[kI11 * kStageSeg];
+        l21 = R[kL21 * kStageSeg];
+        i22 = R[kI22 * kStageSeg];
+        G[0] = R[kG01 * kStageSeg]; G[1] = R[kG02 * kStageSeg]; G[2] = R[kG03 * kStageSeg];
+        G[3] = R[kG11 * kStageSeg]; G[4] = R[kG12 * kStageSeg]; G[5] = R[kG13 * kStageSeg];
+        G[6] = R[kG21 * kStageSeg]; G[7] = R[kG22 * kStageSeg]; G[8] = R[kG23 * kStageSeg];
+        ok = R[kOk * kStageSeg] != 0.0;
     } else {
         const double m00 = (double)Band<TA>::wsum(B, 0);
         const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;

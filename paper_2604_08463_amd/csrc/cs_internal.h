@@ -34,6 +34,8 @@ struct BandDev {
     float ldf[kFMax];
     float lsf[kFMax];
     float wsumf[2];
+    float bcf[kFMax][4];   // (w[0][f], ld[f], ls[f], 0) packed, FP32 copies
+    double bcd[kFMax][4];  // the same in FP64
 };
 
 // One label layout: the labelling of one item, or the labelling shared by every item.

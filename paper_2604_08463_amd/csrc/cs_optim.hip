@@ -362,10 +362,11 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
 }
 
 // The same step with the item's vectors held in registers: thread t owns elements k NT + t,
-// k < PT (K <= NT PT), so every load instruction of a wavefront is one contiguous span.  y, g,
-// the free mask and the direction stay in registers for the whole step, each two-loop pass
-// streams only its pair (s_j, t_j) and keeps the vector the next pass's pending update needs,
-// and every sum is formed in the same order as in k_opt_update.
+// k < PT (K <= NT PT), so every load instruction of a wavefront is one contiguous span.  The free
+// mask and the direction stay in registers for the whole step; each two-loop pass streams only
+// its pair (s_j, t_j), requested during the previous pass's block reduction, and keeps the vector
+// the next pass's pending update needs.  Each thread's partial sums run over its elements in
+// order, as in k_opt_update; the workgroup size (and so the reduction tree) may differ.
 template <int NT, int PT>
 __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
     const int item = blockIdx.x;
@@ -480,35 +481,52 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
 
     if (need_dir) {
         // two-loop recursion on the free set, q (in pv) = P g; carry = t (backward) or s (forward)
-        // of the last used pair, whose update is applied at the start of the next pass
+        // of the last used pair, whose update is applied at the start of the next pass.  Each
+        // pass requests the next pair (s_j, t_j) before its block reduction, so the history stream
+        // overlaps the reductions; y and g are parked in memory meanwhile, and the oldest pair,
+        // last of the backward pass, is the forward pass's first.
         unsigned fr = 0;
         double carry[PT];
 #pragma unroll
         for (int k = 0; k < PT; ++k) {
-            const bool f = ((int64_t)k * NT + tid < K) && is_free(y[k], g[k]);
+            const int64_t i = (int64_t)k * NT + tid;
+            const bool f = (i < K) && is_free(y[k], g[k]);
             fr |= (unsigned)f << k;
             pv[k] = f ? g[k] : 0.0;
             carry[k] = 0.0;
+            if (i < K) {
+                yg[i] = y[k];
+                gg[i] = g[k];
+            }
         }
         const int np = s.npairs, m = a.m;
+        auto pair_at = [&](int c) { return ((s.newest - c) % m + m) % m; };
+        double sn[PT], tn[PT];  // the pair of the coming pass
+        auto fetch = [&](int j) {
+            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                const bool f = (fr >> k) & 1u;
+                sn[k] = f ? Sj[i] : 0.0;
+                tn[k] = f ? Tj[i] : 0.0;
+            }
+        };
+        if (np > 0) fetch(pair_at(0));
         double gamma = 1.0;
         bool gamma_set = false;
         int used = 0;
         bool pend = false;
         double penda = 0.0;
         for (int c = 0; c < np; ++c) {
-            const int j = ((s.newest - c) % m + m) % m;
-            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
+            const int j = pair_at(c);
             double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
                 const bool f = (fr >> k) & 1u;
                 if (pend && f) pv[k] -= penda * carry[k];
-                double ti = 0.0;
+                const double si = sn[k], ti = tn[k];
                 if (f) {
-                    const double si = Sj[i];
-                    ti = Tj[i];
                     v[0] += si * ti;
                     v[1] += si * si;
                     v[2] += ti * ti;
@@ -516,6 +534,7 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
                 }
                 carry[k] = ti;
             }
+            if (c + 1 < np) fetch(pair_at(c + 1));  // the oldest pair stays in sn, tn
             block_sum<4, NT>(v, red);
             if (!(v[0] > 1e-12 * sqrt(v[1]) * sqrt(v[2])) || v[2] == 0.0) {
                 if (tid == 0) rho[j] = 0.0;
@@ -544,27 +563,39 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
         }
         bool spend = false;
         double pendc = 0.0;
-        for (int c = np - 1; c >= 0; --c) {
-            const int j = ((s.newest - c) % m + m) % m;
+        // the forward pass over the pairs with rho != 0, oldest first; sn, tn hold the oldest
+        auto next_used = [&](int c) {
+            while (c >= 0 && rho[pair_at(c)] == 0.0) --c;
+            return c;
+        };
+        int c = next_used(np - 1);
+        if (c >= 0 && c != np - 1) fetch(pair_at(c));
+        while (c >= 0) {
+            const int j = pair_at(c);
             const double rj = rho[j];
-            if (rj == 0.0) continue;
-            const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
             double v[1] = {0.0};
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
                 const bool f = (fr >> k) & 1u;
                 if (spend && f) pv[k] += carry[k] * pendc;
-                double si = 0.0;
-                if (f) {
-                    si = Sj[i];
-                    v[0] += Tj[i] * pv[k];
-                }
+                const double si = sn[k];
+                if (f) v[0] += tn[k] * pv[k];
                 carry[k] = si;
             }
+            const int cn = next_used(c - 1);
+            if (cn >= 0) fetch(pair_at(cn));
             block_sum<1, NT>(v, red);
             spend = true;
             pendc = alp[j] - rj * v[0];
+            c = cn;
+        }
+        // y and g back from memory (the recursion did not hold them)
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int64_t i = (int64_t)k * NT + tid;
+            y[k] = i < K ? yg[i] : 0.0;
+            g[k] = i < K ? gg[i] : 0.0;
         }
         // p = -(H P g) on the free set, p.g, max |p|
         double v[2] = {0.0, 0.0};
@@ -1054,8 +1085,8 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
                         hipLaunchKernelGGL(k_ada_update<1024>, dim3(B), dim3(1024), 0, s, a);
                     else if (kmax <= 64 * 8)
                         hipLaunchKernelGGL((k_opt_update_tile<64, 8>), dim3(B), dim3(64), 0, s, a);
-                    else if (kmax <= 1024 * 8)
-                        hipLaunchKernelGGL((k_opt_update_tile<1024, 8>), dim3(B), dim3(1024), 0, s, a);
+                    else if (kmax <= 512 * 16)
+                        hipLaunchKernelGGL((k_opt_update_tile<512, 16>), dim3(B), dim3(512), 0, s, a);
                     else
                         hipLaunchKernelGGL(k_opt_update<1024>, dim3(B), dim3(1024), 0, s, a);
                     hipError_t eu = hipGetLastError();

@@ -50,22 +50,22 @@ struct Band<float> {
 // BTDT[K_T][F][2] = ((nu/nu0d) expm1(x0)/expm1(x) g(nu)/g(nu0d),  d ln(.)/dT);
 // SS[K_s][F] = (nu/nu0s)^beta_s g(nu)/g(nu0s).  The dust column is PD * BT (eq. mixing_columns).
 // ---------------------------------------------------------------------------------------------
-// Grid: x over an item's (parameter, band) pairs, y over items (from item0): the item is uniform
-// in a workgroup, so its descriptor comes through the scalar cache.
+// Workgroup (nfb, 256 / nfb): x = band group of kSedBands consecutive bands, y = table row;
+// grid x over an item's rows, y over items (from item0).  The item is uniform in a workgroup,
+// so its descriptor comes through the scalar cache.
 constexpr int kSedBands = 4;  // consecutive bands of one table row per thread
+constexpr int kSedThreads = 256;
 
 template <typename TT>
-__global__ __launch_bounds__(256) void k_sed(const EvalArgs a, const int64_t *xoff, int item0) {
+__global__ __launch_bounds__(kSedThreads) void k_sed(const EvalArgs a, const int64_t *xoff, int item0) {
     const int F = a.nfreq;
-    const int nfb = (F + kSedBands - 1) / kSedBands;  // band groups per row
     const int item = item0 + (int)blockIdx.y;
     if (a.active && !as_const(a.active)[item]) return;
     const int64_t x0 = as_const(xoff)[item], kk = as_const(xoff)[item + 1] - x0;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (parameter, band group)
-    if (t == 0) a.istatus[item] = 0;
-    if (t >= kk * nfb) return;
-    const int64_t r = t / nfb;
-    const int fa = (int)(t - r * nfb) * kSedBands;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;  // table row (parameter)
+    if (r == 0 && threadIdx.x == 0) a.istatus[item] = 0;
+    if (r >= kk) return;
+    const int fa = (int)threadIdx.x * kSedBands;
     const int fb = fa + kSedBands < F ? fa + kSedBands : F;
     const cptr<ItemDev> it = as_const(a.items) + item;
     const cptr<BandDev> B = as_const(a.band);
@@ -1100,13 +1100,15 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
 
 cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s) {
     const int64_t *xoff_dev = (const int64_t *)(p->wsp + p->ws.items + sizeof(ItemDev) * (size_t)p->B);
-    const unsigned sblocks = (unsigned)((p->kmax_item * ((p->F + kSedBands - 1) / kSedBands) + 255) / 256);
+    const int nfb = (p->F + kSedBands - 1) / kSedBands;  // band groups per row
+    const int rpb = kSedThreads / nfb;                   // rows per workgroup
+    const unsigned sblocks = (unsigned)((p->kmax_item + rpb - 1) / rpb);
     for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
-        const dim3 grid(sblocks, (unsigned)std::min(kMaxGridY, p->B - b0));
+        const dim3 grid(sblocks, (unsigned)std::min(kMaxGridY, p->B - b0)), block((unsigned)nfb, (unsigned)rpb);
         if (fp32_tables)
-            hipLaunchKernelGGL(k_sed<float>, grid, dim3(256), 0, s, a, xoff_dev, b0);
+            hipLaunchKernelGGL(k_sed<float>, grid, block, 0, s, a, xoff_dev, b0);
         else
-            hipLaunchKernelGGL(k_sed<double>, grid, dim3(256), 0, s, a, xoff_dev, b0);
+            hipLaunchKernelGGL(k_sed<double>, grid, block, 0, s, a, xoff_dev, b0);
         CSI_HIP(hipGetLastError());
     }
     return CS_OK;

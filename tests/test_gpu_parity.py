@@ -304,6 +304,31 @@ def test_optimizer_fp64_matches_oracle_workload3():
         assert np.all(np.abs(xb - xo) <= 1e-4 * np.maximum(1.0, np.abs(xo))), (b, xb, xo)
 
 
+@pytest.mark.parametrize("kd", [7500, 8000])
+def test_optimizer_large_items_follow_oracle(kd):
+    # about 7760 parameters per item take the register-tile update (up to 8192), about 8260 the
+    # update that streams every vector; five iterations from the same start follow the oracle's path
+    sky = skygen.make_config(2, npix=12000, nitems=2, k=(kd, 60, 200))
+    K = int(sky.param_offsets()[1])
+    _log(f"optimizer fp64, {K} parameters per item, 5 iterations")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = prob.cs_optimize_batch(lo, hi, sky.x_packed(), cs.default_opts(max_iter=5))
+    x = r["x"].cpu().numpy()
+    f = r["f"].cpu().numpy()
+    st = r["status"].cpu().numpy()
+    it = r["iters"].cpu().numpy()
+    off = sky.param_offsets()
+    for b in range(sky.nitems):
+        po = oracle.Problem.from_sky(sky, b)
+        xo, fo, ito, _, so = po.lbfgs(sky.x[b], sky.lower[b], sky.upper[b], max_iter=5)
+        xb = x[off[b]:off[b + 1]]
+        _log(f"  item {b}: F {f[b]:.12g} / {fo:.12g}, iters {it[b]} / {ito}, max |dx| {np.max(np.abs(xb - xo)):.2e}")
+        assert st[b] == so and it[b] == ito
+        assert abs(f[b] - fo) <= 1e-10 * abs(fo)
+        assert np.all(np.abs(xb - xo) <= 1e-8 * np.maximum(1.0, np.abs(xo)))
+
+
 def test_optimizer_fp32_bulk_within_1e4_of_fp64():
     sky = skygen.make_config(3, nitems=16)
     _log("optimizer fp32_bulk vs fp64 workload 3 (16 realizations)")

@@ -107,6 +107,26 @@ def test_adatopk_workload3_items_reach_lbfgs_optimum():
     assert np.all(np.abs(r["f"] - f_l) <= 1e-10 * np.abs(f_l))
 
 
+@pytest.mark.parametrize("kd", [300, 1500])
+def test_adatopk_both_workgroup_sizes_follow_oracle(kd):
+    # up to 1024 parameters per item the update runs on 256 threads, above on 1024: five
+    # iterations from the same start follow the oracle's path
+    sky = skygen.make_config(2, npix=6000, nitems=2, k=(kd, 30, 200))
+    off = sky.param_offsets()
+    _log(f"adatopk fp64, {int(off[1])} parameters per item, 5 iterations")
+    prob = cs.Problem.from_sky(sky, "fp64")
+    lo, hi = sky.bounds_packed()
+    r = _run(prob, lo, hi, sky.x_packed(), max_iter=5)
+    for b in range(sky.nitems):
+        sl = slice(off[b], off[b + 1])
+        xo, fo, ito, _, sto = oracle.Problem.from_sky(sky, b).adatopk(sky.x[b], lo[sl], hi[sl], max_iter=5)
+        _log(f"  item {b}: F {r['f'][b]:.12g} / {fo:.12g}, iters {r['iters'][b]} / {ito}, "
+             f"max |dx| {np.max(np.abs(r['x'][sl] - xo)):.2e}")
+        assert r["status"][b] == sto and r["iters"][b] == ito
+        assert abs(r["f"][b] - fo) <= 1e-10 * abs(fo)
+        assert np.all(np.abs(r["x"][sl] - xo) <= 1e-8 * np.maximum(1.0, np.abs(xo)))
+
+
 def test_adatopk_bad_options_rejected():
     sky = skygen.make_tiny(16, 15, (1, 1, 1), seed=3)
     prob = cs.Problem.from_sky(sky, "fp64")

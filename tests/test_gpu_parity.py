@@ -8,7 +8,7 @@ import torch
 
 import skygen
 from oracle import oracle
-from tests._parity import TOL_F, compare, gpu_eval
+from tests._parity import TOL_F, TOL_G, compare, gpu_eval
 
 pytestmark = pytest.mark.gpu
 
@@ -153,24 +153,26 @@ def test_fp32_input_dtype():
     compare(sky, prob, "fp64")
 
 
-def test_separate_stokes_and_pixel_weights():
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_separate_stokes_and_pixel_weights(precision):
     sky = skygen.make_tiny(400, 15, (4, 3, 2), seed=42, nitems=2)
     sky.ninv = sky.ninv.copy()
     sky.ninv[1] *= 1.7  # Q and U weights differ
-    prob = cs.Problem.from_sky(sky, "fp64")
-    compare(sky, prob, "fp64")
+    prob = cs.Problem.from_sky(sky, precision)
+    compare(sky, prob, precision)
     # per-pixel weights: the oracle gets the same [2][F][P] array
     g = np.random.default_rng(5)
     wpix = sky.ninv[:, :, None] * g.uniform(0.5, 2.0, (2, sky.nfreq, sky.npix))
     prob2 = cs.Problem(sky.freqs, sky.d.cuda(), torch.as_tensor(wpix[None]).cuda(), sky.labels.cuda(),
-                       sky.nclusters, nitems=sky.nitems, precision="fp64")
+                       sky.nclusters, nitems=sky.nitems, precision=precision)
     f, gr, _, st = gpu_eval(prob2, sky, cluster=False)
     off = sky.param_offsets()
     for b in range(sky.nitems):
         pr = oracle.Problem(sky.freqs, sky.item_d(b), wpix, sky.item_labels(b), sky.nclusters[b])
         fo, go, _, so = pr.likelihood_grad(sky.x[b])
-        assert abs(f[b] - fo) <= 1e-12 * abs(fo)
-        assert np.max(np.abs(gr[off[b]:off[b + 1]] - go)) <= 1e-9 * np.max(np.abs(go))
+        assert st[b] == so
+        assert abs(f[b] - fo) <= TOL_F[precision] * abs(fo)
+        assert np.max(np.abs(gr[off[b]:off[b + 1]] - go)) <= TOL_G[precision] * np.max(np.abs(go))
 
 
 def test_not_pd_status_and_nan():
@@ -226,12 +228,17 @@ def test_batched_equals_per_item_and_schedules_bit_identical():
                     assert np.array_equal(f2, ref[0]) and np.array_equal(g2, ref[1])
 
 
-def test_likelihood_without_gradient_matches():
+@pytest.mark.parametrize("shared", [1, 0])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk", "fp32_store"])
+def test_likelihood_without_gradient_matches(precision, shared):
+    # the F-only kernels accumulate M and b as the gradient kernels do
     sky = skygen.make_config(2, npix=5000, nitems=3, k=(100, 10, 20))
-    prob = cs.Problem.from_sky(sky, "fp64")
-    f, _, _, _ = gpu_eval(prob, sky, cluster=False)
-    f2, st = prob.cs_likelihood(torch.as_tensor(sky.x_packed(), device="cuda"))
-    f2 = f2.cpu().numpy()
+    prob = cs.Problem.from_sky(sky, precision)
+    prob.set_schedule(2, 0, 0, shared)
+    f, _, _, st = gpu_eval(prob, sky, cluster=False)
+    f2, st2 = prob.cs_likelihood(torch.as_tensor(sky.x_packed(), device="cuda"))
+    f2, st2 = f2.cpu().numpy(), st2.cpu().numpy()
+    assert np.array_equal(st2, st)
     assert np.all(np.abs(f2 - f) <= 1e-13 * np.abs(f))
 
 

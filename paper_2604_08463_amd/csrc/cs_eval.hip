@@ -1,12 +1,14 @@
 // One batched evaluation of the spectral likelihood and its adjoint (paper Sec. 2.1, 3.3.1).
 //
-//   k_sed       per (item, cluster): SED tables of the three spectral parameters (a2)
-//   k_pixel     per 64-pixel chunk (one wavefront): label gather -> mixing matrix in registers
-//               (a3), frequency accumulation of A^T N^-1 A, A^T N^-1 d and the adjoint sums (a4),
-//               FP64 3x3 Cholesky (a5), per-pixel gradient (a6), run-segmented wave reduction
-//               (a7, first level)
-//   k_fin_grad  per (item, cluster): compensated sum over the cluster's segments (a7)
-//   k_fin_f     per item: compensated sum of F and the status word (a7)
+//   k_sed          per (item, cluster, band group): SED tables of the three spectral parameters (a2)
+//   k_pixel_stage  per 64-pixel chunk (one wavefront): the chunk's SED columns staged in LDS, the
+//                  mixing matrix per pixel (a3), frequency accumulation of A^T N^-1 A, A^T N^-1 d
+//                  and the adjoint sums (a4), FP64 3x3 Cholesky (a5), per-pixel gradient (a6),
+//                  run-segmented wave reduction (a7, first level); k_pixel is the direct-gather
+//                  form for per-Stokes or per-pixel weights
+//   k_fin_grad     per (item, cluster): compensated sum over the cluster's segments, and F of
+//                  each item in slices of its segments (a7)
+//   k_fin_f        per item: the slices of F folded in order, and the status word (a7)
 //
 // Gradient without a second pass over the data.  With r_s = N^-1 (d_s - A s_hat_s) and
 // delta_k(nu) = dA/dtheta_k (only one column depends on theta_k),

@@ -105,6 +105,50 @@ def time_eval(prob, x, steps, warmup, timing=True, label=None):
     return (t1 - t0), kms, nl, out
 
 
+def maps_leg(prob, x, reps=5):
+    """Component maps and sigma^2_CMB of every item at x: items per second and the bytes moved
+    (the stored data read once, the six FP64 maps written)."""
+    prob.cs_component_maps(x)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.cs_component_maps(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    pix = prob.nitems * prob.npix
+    nbytes = pix * (2 * prob.nfreq * 4 + 6 * 8)
+    return dict(items_per_s=prob.nitems / dt, ms_per_call=dt * 1e3, bytes_per_call=nbytes,
+                achieved_gbs=nbytes / dt / 1e9)
+
+
+def kmeans_leg(ntask=1024, npix=3072, iters=20, seed=2604):
+    """One batched call of spherical K-means patching shaped like the configuration scan: ntask
+    tasks on npix positions, latitude masks with f_sky in [0.4, 0.8], K in [10, 3000] (seeded)."""
+    import paper_2604_08463_amd as cs
+    import skygen
+    g = np.random.default_rng(seed)
+    v = skygen.sky.positions(npix, g)
+    ks = g.integers(10, 3001, ntask).astype(np.int32)
+    fsky = g.uniform(0.4, 0.8, ntask)
+    keep = np.stack([skygen.latitude_mask(v[:, 2], f) for f in fsky])
+    init = np.zeros((ntask, int(ks.max())), dtype=np.int32)
+    for t in range(ntask):
+        nk = int(keep[t].sum())
+        if ks[t] < nk:
+            init[t, :ks[t]] = g.choice(nk, size=int(ks[t]), replace=False)
+    vt = torch.as_tensor(v, device="cuda")
+    it = torch.as_tensor(init, device="cuda")
+    kt = torch.as_tensor(keep.astype(np.uint8), device="cuda")
+    cs.kmeans_batch(vt, ks[:4], it[:4], kt[:4], iters=iters)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, keff = cs.kmeans_batch(vt, ks, it, kt, iters=iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(tasks=ntask, npix=npix, iters=iters, k_range=[10, 3000], fsky_range=[0.4, 0.8], time_s=dt,
+                tasks_per_s=ntask / dt, keff_mean=float(keff.float().mean().item()))
+
+
 def cpu_baseline(sky, x_items, budget_s: float = 12.0):
     from oracle import oracle
 
@@ -131,6 +175,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-optimizer", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-maps", action="store_true")
+    ap.add_argument("--no-kmeans", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="kernel-profiling run: only the timed evaluations of one precision")
@@ -291,6 +337,21 @@ def main():
                        maxiter=int(np.sum(st & cs.MAXITER > 0)), f_mean=float(r["f"].mean().item()))
         log(f"optimizer (AdaTopK): {opt_ada}")
 
+    maps = None
+    if not args.no_maps:
+        pm = cs.Problem.from_sky(sky, "fp32_bulk")
+        if sched:
+            pm.set_schedule(**sched)
+        maps = maps_leg(pm, x)
+        log(f"component maps: {maps}")
+        del pm
+        torch.cuda.empty_cache()
+
+    km = None
+    if not args.no_kmeans:
+        km = kmeans_leg()
+        log(f"k-means: {km}")
+
     cpu = None
     if not args.no_cpu_baseline:
         n, t = cpu_baseline(sky, x_items)
@@ -327,6 +388,8 @@ def main():
         "prep_ms": prep_ms,
         "optimizer": opt,
         "optimizer_adatopk": opt_ada,
+        "component_maps": maps,
+        "kmeans": km,
     }
     print(json.dumps(line), flush=True)
 

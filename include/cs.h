@@ -244,7 +244,8 @@ cs_status cs_problem_get_schedule(const cs_problem *prob, cs_schedule *sched);
 cs_status cs_problem_set_schedule(cs_problem *prob, const cs_schedule *sched);
 
 /* Times every candidate schedule on cs_likelihood_grad at x (reps evaluations each, HIP
- * events on the stream) and keeps the fastest.  Candidates that only move work between
+ * events on the stream), then re-times the four fastest in turn over three rounds of
+ * max(reps, 5) evaluations and keeps the one with the least total.  Candidates that only move work between
  * wavefronts must reproduce the current schedule's F bit for bit; candidates that change
  * shared_segments (a different rounding order) must agree to 1e-11 relative (1e-6 for
  * CS_FP32_BULK); others are rejected.  grad / neg2logL are scratch outputs.  Writes

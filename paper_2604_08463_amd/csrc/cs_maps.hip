@@ -61,23 +61,23 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
     const int item = __builtin_amdgcn_readfirstlane(a.units[u].x);
     const int chunk = __builtin_amdgcn_readfirstlane(a.units[u].y);
     const int F = a.nfreq;
-    const ItemDev &it = a.items[item];
-    const LayoutDev &L = a.layouts[it.layout];
-    const uint64_t head = L.head[chunk];
-    const int segbase = L.seg_base[chunk];
-    const int nvalid = min(L.n_incl - chunk * kChunk, kChunk);
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
+    const uint64_t head = as_const(L->head)[chunk];
+    const int segbase = as_const(L->seg_base)[chunk];
+    const int nvalid = min(L->n_incl - chunk * kChunk, kChunk);
     const bool valid = lane < nvalid;
     const int seg = segbase + __popcll(head & lanemask_le(lane)) - 1;
-    const int *lab = (const int *)L.seg_lab + 4 * (int64_t)seg;
-    const int64_t kd = it.k[0], kt = it.k[1];
-    const double *tab = (const double *)a.tables + it.tab_off * (int64_t)F;
-    const double *pd = tab + (int64_t)lab[0] * F;
-    const double *bt = tab + (kd + 2 * (int64_t)lab[1]) * F;
-    const double *ss = tab + (kd + 2 * kt + lab[2]) * F;
-    const int64_t cbase = (it.dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
-    const TS *dq = (const TS *)a.dpack + cbase;
-    const TS *wq = (wm == 2) ? (const TS *)a.wpack + cbase : nullptr;
-    const BandDev &B = *a.band;
+    const gptr<int> lab = as_global((const int *)L->seg_lab) + 4 * (int64_t)seg;
+    const int64_t kd = it->k[0], kt = it->k[1];
+    const gptr<double> tab = as_global((const double *)a.tables) + it->tab_off * (int64_t)F;
+    const gptr<double> pd = tab + (int64_t)lab[0] * F;
+    const gptr<double> bt = tab + (kd + 2 * (int64_t)lab[1]) * F;
+    const gptr<double> ss = tab + (kd + 2 * kt + lab[2]) * F;
+    const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
+    const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
+    const gptr<TS> wq = (wm == 2) ? as_global((const TS *)a.wpack) + cbase : nullptr;
+    const cptr<BandDev> B = as_const(a.band);
 
     // normal equations per Stokes parameter: M (upper triangle) and b, in FP64
     double m[2][6], b[2][3];
@@ -85,24 +85,32 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
         for (int i = 0; i < 6; ++i) m[s][i] = 0.0;
         for (int i = 0; i < 3; ++i) b[s][i] = 0.0;
     }
+    // bands four at a time, so that their gathers and data loads are in flight together; with
+    // band weights shared by Q and U (wm == 0) the U sums of M equal the Q sums and are copied
+#pragma unroll 4
     for (int f = 0; f < F; ++f) {
         const double ad = pd[f] * bt[2 * f], as = ss[f];
+#pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int64_t o = ((int64_t)s * F + f) * kChunk;
-            const double w = (wm == 2) ? (double)wq[o] : B.w[s][f];
+            const double w = (wm == 2) ? (double)wq[o] : B->w[s][f];
             const double dv = (double)dq[o];
             const double wad = w * ad, was = w * as;
-            m[s][0] += w;
-            m[s][1] += wad;
-            m[s][2] += was;
-            m[s][3] += wad * ad;
-            m[s][4] += wad * as;
-            m[s][5] += was * as;
+            if (wm != 0 || s == 0) {
+                m[s][0] += w;
+                m[s][1] += wad;
+                m[s][2] += was;
+                m[s][3] += wad * ad;
+                m[s][4] += wad * as;
+                m[s][5] += was * as;
+            }
             b[s][0] += w * dv;
             b[s][1] += wad * dv;
             b[s][2] += was * dv;
         }
     }
+    if (wm == 0)
+        for (int i = 0; i < 6; ++i) m[1][i] = m[0][i];
     double sh[2][3];
     bool ok = true;
     for (int s = 0; s < 2; ++s) {
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
     if (__ballot(valid && !ok) && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
 
     if (maps && valid) {
-        const int32_t pix = L.order[chunk * kChunk + lane];
+        const int32_t pix = L->order[chunk * kChunk + lane];
         double *o = maps + (int64_t)item * stride + pix;
         for (int s = 0; s < 2; ++s)
             for (int c = 0; c < 3; ++c) o[(int64_t)(3 * s + c) * npix] = sh[s][c];
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
     const double eq = valid ? vq - mq : 0.0, eu = valid ? vu - mu : 0.0;
     const double sq = wave_sum(eq * eq), su = wave_sum(eu * eu);
     if (lane == 0) {
-        double *st = a.partials + it.part_off * 4 + (int64_t)chunk * 8;
+        double *st = a.partials + it->part_off * 4 + (int64_t)chunk * 8;
         st[0] = n;
         st[1] = mq;
         st[2] = sq;
@@ -198,7 +206,7 @@ cs_status launch_maps(cs_problem *p, const double *x, double *maps, int64_t maps
                            per_item, total);
         CSI_HIP(hipGetLastError());
     }
-    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : 1;
+    const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
     if (p->nunits > 0) {
         const dim3 grid((unsigned)((p->nunits + kMapWaves - 1) / kMapWaves)), block(64 * kMapWaves);
         if (p->prec == CS_FP64)

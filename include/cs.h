@@ -48,11 +48,11 @@ typedef enum {
 
 /* Working precision of the per-pixel data stream (d and per-pixel N^-1).
  *   CS_FP64       : FP64 storage, FP64 frequency accumulation, FP64 solve and reductions.
- *   CS_FP32_BULK  : FP32 storage, FP32 frequency accumulation of every sum that involves the
- *                   data (A^T N^-1 d and its adjoint counterparts), FP64 3x3 Cholesky solve,
- *                   FP64 compensated per-cluster reductions.  The data-free sums (A^T N^-1 A and
- *                   the adjoint sums A^T N^-1 dA) are formed in FP64 once per segment when the
- *                   schedule shares them (cs_schedule.shared_segments), else in FP32 per pixel.
+ *   CS_FP32_BULK  : FP32 storage and FP32 frequency accumulation of every per-band sum
+ *                   (A^T N^-1 A, A^T N^-1 d and the adjoint sums), whichever schedule forms them
+ *                   (per pixel, per segment inside the pixel kernel, or per segment in a
+ *                   pre-pass); FP64 3x3 Cholesky solve from those sums; FP64 compensated
+ *                   per-cluster reductions.
  *   CS_FP32_STORE : FP32 storage, FP64 accumulation, solve and reductions.  */
 typedef enum { CS_FP64 = 0, CS_FP32_BULK = 1, CS_FP32_STORE = 2 } cs_precision;
 
@@ -118,19 +118,29 @@ cs_status cs_problem_prepare(cs_problem *prob, void *workspace, size_t bytes, vo
 cs_status cs_problem_item_info(const cs_problem *prob, int32_t item, int64_t *n_included,
                                int64_t *n_segments);
 
-/* Segment structure of one labelling (0 = beta_d, 1 = T_d, 2 = beta_s) of one item, for
- * bit-exact checks: perm[n_included] lists the included pixel indices grouped by cluster,
+/* Segment structure of one labelling (0 = beta_d, 1 = T_d, 2 = beta_s) of one item (paper
+ * Sec. 2.2: each patch is a disjoint set of pixels sharing one parameter value; Sec. 2.3: one
+ * patching per spectral parameter), for bit-exact checks: perm[n_included] lists the included pixel indices grouped by cluster,
  * ascending pixel index inside a cluster (a stable sort by label); offsets[K_j + 1] is the
  * exclusive prefix sum of cluster sizes.  Device outputs; enqueued on the stream. */
 cs_status cs_problem_segments(cs_problem *prob, int32_t item, int32_t labeling, int32_t *perm,
                               int32_t *offsets, void *stream);
 
-/* neg2logL[B] = F of each item at x (packed, FP64).  status[B] (nullable) gets the item bits.
+/* neg2logL[B] = F of each item at x (packed, FP64): the spectral likelihood of paper Sec. 2.1,
+ * eq. spectral_likelihood, with s profiled out by the GLS solution of eq. mle_solution, and
+ * the parameters of each pixel read through its three patch labels (Sec. 2.2-2.3).  The 3x3
+ * system per pixel is solved by an FP64 Cholesky factorisation (the central step of Sec.
+ * 3.3.1).  status[B] (nullable) gets the item bits; a pixel whose A^T N^-1 A fails the
+ * positive-definiteness test sets CS_ITEM_NOT_PD and F = NaN; a non-finite F sets
+ * CS_ITEM_NONFINITE.  x, neg2logL and status are caller-owned device arrays.
  * Asynchronous on the stream; no allocation; capturable in a HIP graph. */
 cs_status cs_likelihood(cs_problem *prob, const double *x, double *neg2logL, int32_t *status,
                         void *stream);
 
-/* As cs_likelihood, plus grad (packed like x) = dF/dx summed per cluster, and optional
+/* As cs_likelihood, plus grad (packed like x) = dF/dx summed per cluster (the adjoint of
+ * paper Sec. 3.3.1: the gradient of the profiled likelihood with the GLS amplitudes held fixed,
+ * -2 r^T (dA/dtheta) s_hat with r = N^-1 (d - A s_hat), routed to each parameter's patch by
+ * summing over its pixels), and optional
  * cluster_neg2logL (nullable, packed like x): entry k of labelling j is the sum of the
  * per-pixel terms of F over the pixels of cluster k of labelling j (each labelling's entries
  * sum to F).  Per-cluster sums are FP64 and compensated. */
@@ -245,11 +255,12 @@ cs_status cs_problem_set_schedule(cs_problem *prob, const cs_schedule *sched);
 
 /* Times every candidate schedule on cs_likelihood_grad at x (reps evaluations each, HIP
  * events on the stream), then re-times the four fastest in turn over three rounds of
- * max(reps, 5) evaluations and keeps the one with the least total.  Candidates that only move work between
- * wavefronts must reproduce the current schedule's F bit for bit; candidates that change
- * shared_segments (a different rounding order) must agree to 1e-11 relative (1e-6 for
- * CS_FP32_BULK); others are rejected.  grad / neg2logL are scratch outputs.  Writes
- * the chosen schedule to *best (nullable).  Synchronises the stream. */
+ * max(reps, 5) evaluations and keeps the one with the least total.  Candidates that only move
+ * work between wavefronts must reproduce the current schedule's F and gradient bit for bit;
+ * candidates that change shared_segments (a different rounding order) must agree on F to 1e-11
+ * relative and on each item's gradient to 1e-8 normwise (1e-6 and 1e-3 for CS_FP32_BULK);
+ * others are rejected.  grad / neg2logL are scratch outputs.  Writes the chosen schedule to
+ * *best (nullable).  Synchronises the stream. */
 cs_status cs_problem_autotune(cs_problem *prob, const double *x, double *neg2logL, double *grad,
                               int32_t reps, cs_schedule *best, void *stream);
 

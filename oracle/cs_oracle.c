@@ -147,7 +147,6 @@ static int orc_lu_solve3(const double m[9], const double b[3], double xout[3]) {
     return 0;
 }
 
-/* positive definiteness by Sylvester's criterion: all leading principal minors > 0 */
 /* Positive definiteness of the symmetric 3x3 M (Sylvester's criterion, read numerically): each
  * leading principal minor must be positive relative to the product of its diagonal entries,
  * minor_k > ORC_PD_REL * m_00 ... m_kk, so that a rank-deficient M (fewer bands than components,
@@ -306,6 +305,53 @@ int orc_grad_abs(const orc_problem *pr, const double *x, double *gabs) {
         double f, g[3];
         status |= orc_pixel(pr, x, (int32_t)p, NULL, NULL, NULL, NULL, &f, g);
         for (int j = 0; j < 3; ++j) gabs[off[j] + pr->labels[j * P + p]] += fabs(g[j]);
+    }
+    return status;
+}
+
+/*
+ * Magnitude of the terms that make up each cluster's gradient (packed like grad): with the
+ * residual expanded, r_nu = w_nu (d_nu - sum_j a_j(nu) s_j), a pixel's derivative is a signed sum
+ * of the terms -2 w (dA/dtheta)_nu s_c d_nu and +2 w (dA/dtheta)_nu s_c a_j(nu) s_j, and
+ *     gterm[k] = sum over the cluster's pixels, both Stokes parameters and all bands of
+ *                2 |s_c| w |(dA/dtheta)_nu| (|d_nu| + sum_j |a_j(nu)| |s_j|).
+ * A sum of these terms accumulated in a working precision of unit roundoff u is in error by at
+ * most about (number of terms) u gterm[k] whatever their cancellation, so the FP32 tolerances
+ * are stated against it.  gterm[k] >= gabs[k] (triangle inequality).  Plain sums in ascending
+ * pixel order.  Returns status bits (>= 0) or a negative error code.
+ */
+int orc_grad_terms(const orc_problem *pr, const double *x, double *gterm) {
+    int rc = orc_check_labels(pr);
+    if (rc) return rc;
+    const int F = pr->nfreq;
+    const int64_t P = pr->npix;
+    const int K = pr->nclusters[0] + pr->nclusters[1] + pr->nclusters[2];
+    const int off[3] = {0, pr->nclusters[0], pr->nclusters[0] + pr->nclusters[1]};
+    for (int k = 0; k < K; ++k) gterm[k] = 0.0;
+    int status = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (pr->labels[p] < 0) continue;
+        double sh[6];
+        status |= orc_pixel(pr, x, (int32_t)p, NULL, NULL, sh, NULL, NULL, NULL);
+        const double beta_d = x[pr->labels[p]];
+        const double temp_d = x[off[1] + pr->labels[P + p]];
+        const double beta_s = x[off[2] + pr->labels[2 * P + p]];
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int n = 0; n < F; ++n) {
+            double ad, as, dbd, dtd, dbs;
+            orc_sed(pr->freqs[n], pr->nu0_dust, pr->nu0_sync, pr->tcmb, beta_d, temp_d, beta_s, &ad, &as, &dbd,
+                    &dtd, &dbs);
+            for (int s = 0; s < 2; ++s) {
+                const double w = pr->ninv_per_pixel ? pr->ninv[((int64_t)s * F + n) * P + p] : pr->ninv[s * F + n];
+                const double dv = pr->d[((int64_t)s * F + n) * P + p];
+                const double *q = sh + 3 * s;
+                const double mag = w * (fabs(dv) + fabs(q[0]) + fabs(ad) * fabs(q[1]) + fabs(as) * fabs(q[2]));
+                t[0] += 2.0 * fabs(q[1]) * fabs(dbd) * mag;
+                t[1] += 2.0 * fabs(q[1]) * fabs(dtd) * mag;
+                t[2] += 2.0 * fabs(q[2]) * fabs(dbs) * mag;
+            }
+        }
+        for (int j = 0; j < 3; ++j) gterm[off[j] + pr->labels[j * P + p]] += t[j];
     }
     return status;
 }

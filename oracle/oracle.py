@@ -60,6 +60,7 @@ def lib():
         L.orc_pixel.argtypes = [P(_Problem), dp, C.c_int32, dp, dp, dp, dp, dp, dp]
         L.orc_likelihood_grad.argtypes = [P(_Problem), dp, dp, dp, dp]
         L.orc_grad_abs.argtypes = [P(_Problem), dp, dp]
+        L.orc_grad_terms.argtypes = [P(_Problem), dp, dp]
         L.orc_component_maps.argtypes = [P(_Problem), dp, dp, dp]
         L.orc_data_chi2.argtypes = [P(_Problem)]
         L.orc_data_chi2.restype = C.c_double
@@ -133,6 +134,18 @@ class Problem:
         if st < 0:
             raise ValueError(f"oracle error {st}")
         return ga
+
+    def grad_terms(self, x):
+        """Per cluster (packed like the gradient) the summed magnitude of the terms its gradient
+        is built from (|s_c| w |dA/dtheta| (|d| + |A||s|) over pixels, Stokes and bands): the scale
+        of the rounding error of sums accumulated in reduced precision."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.size == self.K
+        gt = np.zeros(self.K)
+        st = lib().orc_grad_terms(C.byref(self._s), _dp(x), _dp(gt))
+        if st < 0:
+            raise ValueError(f"oracle error {st}")
+        return gt
 
     def pixel(self, x, p: int):
         """Per-pixel details: dict(M [2,3,3], b [2,3], s [2,3], r [2,F], f, g [3], status)."""

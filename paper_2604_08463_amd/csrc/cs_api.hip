@@ -490,19 +490,42 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
     const cs_schedule keep = p->sched;
     const bool was_timing = p->timing;
     p->timing = false;
-    std::vector<double> ref(p->B), got(p->B);
+    const size_t K = (size_t)p->xoff[p->B];
+    std::vector<double> ref(p->B), got(p->B), refg(K), gotg(K);
     hipEvent_t e0, e1;
     CSI_HIP(hipEventCreate(&e0));
     CSI_HIP(hipEventCreate(&e1));
     cs_status rc = launch_eval(p, x, nullptr, neg2logl, grad, nullptr, nullptr, true, p->prec, s);
-    if (rc == CS_OK && hipMemcpyAsync(ref.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (rc == CS_OK && (hipMemcpyAsync(ref.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipMemcpyAsync(refg.data(), grad, sizeof(double) * K, hipMemcpyDeviceToHost, s) != hipSuccess))
         rc = CS_E_HIP;
     if (rc == CS_OK && hipStreamSynchronize(s) != hipSuccess) rc = CS_E_HIP;
     cs_schedule bestsch = keep;
     std::vector<std::pair<float, cs_schedule>> cand;  // (time, schedule) of every agreeing schedule
     const int waves[4] = {1, 2, 4, 8};
     const int bpc[3] = {0, 2, 4};
+    // tolerances across the two rounding orders (per-pixel or per-segment sums): F relative, and
+    // the gradient normwise per item
     const double cross_tol = p->prec == CS_FP32_BULK ? 1e-6 : 1e-11;
+    const double cross_gtol = p->prec == CS_FP32_BULK ? 1e-3 : 1e-8;
+    // a candidate is kept only when F and the gradient of every item agree with the reference
+    auto agrees = [&](bool same_arith) {
+        if (same_arith)  // same arithmetic, work only moved between wavefronts: bit-identical
+            return std::memcmp(got.data(), ref.data(), sizeof(double) * p->B) == 0 &&
+                   std::memcmp(gotg.data(), refg.data(), sizeof(double) * K) == 0;
+        for (int b = 0; b < p->B; ++b) {
+            if (!(std::fabs(got[b] - ref[b]) <= cross_tol * std::fabs(ref[b]))) return false;
+            double gm = 0.0, dm = 0.0;
+            for (int64_t i = p->xoff[b]; i < p->xoff[b + 1]; ++i) {
+                gm = std::max(gm, std::fabs(refg[i]));
+                const double dv = std::fabs(gotg[i] - refg[i]);
+                if (!(dv == dv)) return false;  // NaN
+                dm = std::max(dm, dv);
+            }
+            if (!(dm <= cross_gtol * gm)) return false;
+        }
+        return true;
+    };
     for (int sh = 0; sh < 2 && rc == CS_OK; ++sh)
         for (int wi = 0; wi < 4 && rc == CS_OK; ++wi)
             for (int bi = 0; bi < 3 && rc == CS_OK; ++bi)
@@ -517,19 +540,12 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
                     float ms = 0.f;
                     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
-                        hipMemcpy(got.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost) != hipSuccess) {
+                        hipMemcpy(got.data(), neg2logl, sizeof(double) * p->B, hipMemcpyDeviceToHost) != hipSuccess ||
+                        hipMemcpy(gotg.data(), grad, sizeof(double) * K, hipMemcpyDeviceToHost) != hipSuccess) {
                         rc = CS_E_HIP;
                         break;
                     }
-                    bool agree = true;
-                    if (sh == keep.shared_segments) {
-                        // same arithmetic, work only moved between wavefronts: bit-identical
-                        agree = std::memcmp(got.data(), ref.data(), sizeof(double) * p->B) == 0;
-                    } else {
-                        for (int b = 0; b < p->B; ++b)
-                            if (!(std::fabs(got[b] - ref[b]) <= cross_tol * std::fabs(ref[b]))) agree = false;
-                    }
-                    if (agree) cand.emplace_back(ms, p->sched);
+                    if (agrees(sh == keep.shared_segments)) cand.emplace_back(ms, p->sched);
                 }
     // second stage: the four fastest re-timed in turn over three rounds with more repetitions, so
     // that one noisy timing does not decide

@@ -1,8 +1,8 @@
 """Seeded LiteBIRD-shaped synthetic skies (stand-ins for the paper's PySM3 / Planck / LiteBIRD inputs).
 
 Every array is drawn from NumPy ``PCG64`` streams seeded by
-``SeedSequence([2604, 8463, config_id, stream_id, *sub])`` (heavy draws of noise on a GPU use a
-torch Philox generator seeded from the same sequence).  The simulated sky follows the paper's data
+``SeedSequence([2604, 8463, config_id, stream_id, *sub])``, on the host for every target device
+(a GPU workload holds the same numbers as its CPU copy).  The simulated sky follows the paper's data
 model (Sec. 2.1, eq. data_model): per pixel, multi-band Q/U data equal to CMB + dust + synchrotron
 plus white noise.
 
@@ -16,6 +16,8 @@ HIP library uses this code: each builds its own mixing matrix.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -42,13 +44,6 @@ _STREAM = dict(pos=0, cmb=1, dust=2, sync=3, field_bd=4, field_td=5, field_bs=6,
 def _rng(cid: int, stream: str, *sub: int) -> np.random.Generator:
     seq = np.random.SeedSequence([2604, 8463, int(cid), _STREAM[stream], *[int(s) for s in sub]])
     return np.random.Generator(np.random.PCG64(seq))
-
-
-def _torch_gen(cid: int, stream: str, device, *sub: int) -> torch.Generator:
-    seed = int(np.random.SeedSequence([2604, 8463, int(cid), _STREAM[stream], *sub]).generate_state(1, np.uint64)[0])
-    g = torch.Generator(device=device)
-    g.manual_seed(seed & 0x7FFFFFFFFFFFFFFF)
-    return g
 
 
 # ----------------------------------------------------------------------------------------------
@@ -297,16 +292,22 @@ def _signal(freqs, truth, cmb, dust, sync, nu0d=NU0_DUST, nu0s=NU0_SYNC) -> np.n
 
 
 def _noise(cid: int, sigma: np.ndarray, nreal: int, npix: int, device, first: int = 0) -> torch.Tensor:
-    """White noise ``[R][2][F][P]``: NumPy PCG64 on the CPU, torch Philox on a GPU."""
+    """White noise ``[R][2][F][P]``: realization ``r`` is drawn from its own NumPy ``PCG64`` stream
+    ``(cid, noise, first + r)`` on the host whatever the target device, so a GPU workload and its
+    CPU copy hold the same numbers.  Realizations are drawn on a few threads (the generator
+    releases the GIL) and copied to the device in groups."""
     f = sigma.size
-    if torch.device(device).type == "cpu":
-        out = np.empty((nreal, 2, f, npix))
-        for r in range(nreal):
-            out[r] = _rng(cid, "noise", first + r).standard_normal((2, f, npix)) * sigma[None, :, None]
-        return torch.from_numpy(out)
-    gen = _torch_gen(cid, "noise", device, first)
-    n = torch.randn((nreal, 2, f, npix), dtype=torch.float64, device=device, generator=gen)
-    return n * torch.as_tensor(sigma, dtype=torch.float64, device=device).view(1, 1, f, 1)
+    out = torch.empty((nreal, 2, f, npix), dtype=torch.float64, device=device)
+
+    def draw(r):
+        return _rng(cid, "noise", first + r).standard_normal((2, f, npix)) * sigma[None, :, None]
+
+    group = 8
+    with ThreadPoolExecutor(max_workers=min(group, max(1, os.cpu_count() or 1))) as ex:
+        for r0 in range(0, nreal, group):
+            parts = list(ex.map(draw, range(r0, min(nreal, r0 + group))))
+            out[r0:r0 + len(parts)] = torch.from_numpy(np.stack(parts)).to(device)
+    return out
 
 
 def _field_truth(cid, vecs, ell_deg, device):

@@ -8,7 +8,7 @@ import torch
 
 import skygen
 from oracle import oracle
-from tests._parity import TOL_F, TOL_G, compare, gpu_eval
+from tests._parity import TOL_F, check_grad, compare, gpu_eval
 
 pytestmark = pytest.mark.gpu
 
@@ -172,7 +172,8 @@ def test_separate_stokes_and_pixel_weights(precision):
         fo, go, _, so = pr.likelihood_grad(sky.x[b])
         assert st[b] == so
         assert abs(f[b] - fo) <= TOL_F[precision] * abs(fo)
-        assert np.max(np.abs(gr[off[b]:off[b + 1]] - go)) <= TOL_G[precision] * np.max(np.abs(go))
+        check_grad(precision, sky.nfreq, gr[off[b]:off[b + 1]], go,
+                   pr.grad_terms(sky.x[b]) if precision != "fp64" else None)
 
 
 def test_not_pd_status_and_nan():
@@ -435,17 +436,19 @@ def test_workload5_full_size_sampled_items():
     off = sky.param_offsets()
     picks = (0, 37)
     ref = {b: oracle.Problem.from_sky(sky, b).likelihood_grad(sky.x[b]) for b in picks}
-    for precision, tf, tg in (("fp32_bulk", 1e-5, 1e-2), ("fp64", 1e-12, 1e-9)):
+    terms = {b: oracle.Problem.from_sky(sky, b).grad_terms(sky.x[b]) for b in picks}
+    for precision, tf in (("fp32_bulk", 1e-5), ("fp64", 1e-12)):
         prob = cs.Problem.from_sky(sky, precision)
         s = prob.autotune(x, reps=1)
         f, g, _, st = gpu_eval(prob, sky, cluster=False)
         for b in picks:
             fo, go, _, so = ref[b]
             ef = abs(f[b] - fo) / abs(fo)
-            eg = np.max(np.abs(g[off[b]:off[b + 1]] - go)) / np.max(np.abs(go))
             _log(f"workload 5 {precision} schedule ({s.waves_per_block},{s.blocks_per_cu},{s.xcd_remap},"
-                 f"{s.shared_segments}) item {b}: rel F {ef:.2e} grad {eg:.2e}")
-            assert st[b] == so and ef <= tf and eg <= tg
+                 f"{s.shared_segments}) item {b}: rel F {ef:.2e}")
+            assert st[b] == so and ef <= tf
+            eg, r = check_grad(precision, sky.nfreq, g[off[b]:off[b + 1]], go, terms[b])
+            _log(f"  gradient normwise {eg:.2e}, worst ratio to the FP32 bound {r:.3f}")
         assert np.all(np.isfinite(f)) and np.all(st == 0)
         del prob
         torch.cuda.empty_cache()

@@ -304,6 +304,42 @@ def test_gradient_abs_scale_of_clusters():
     assert np.allclose(ga[single], np.abs(g[single]), rtol=1e-15, atol=0)
 
 
+def test_gradient_term_magnitudes():
+    # the FP32 tolerance scale: every signed term of a cluster's gradient enumerated one by one
+    # (pixel, Stokes, band; the data term and the three model terms of the expanded residual).
+    # Their signed sum must give the complex-step-pinned gradient -- so the enumeration is
+    # complete -- and the sum of their magnitudes is gterm; it bounds gabs and |grad| from above
+    sky = skygen.make_tiny(6, 5, (2, 2, 3), seed=12)
+    pr = O.Problem.from_sky(sky)
+    x = sky.x[0]
+    _, g, _, _ = pr.likelihood_grad(x)
+    gt = pr.grad_terms(x)
+    ga = pr.grad_abs(x)
+    lab = sky.item_labels(0)
+    d = sky.item_d(0)
+    K = sky.nclusters[0]
+    off = [0, K[0], K[0] + K[1]]
+    signed = np.zeros_like(g)
+    mags = np.zeros_like(g)
+    for p in range(sky.npix):
+        bd, td, bs = x[lab[0, p]], x[off[1] + lab[1, p]], x[off[2] + lab[2, p]]
+        sh = pr.pixel(x, p)["s"]
+        for n, nu in enumerate(sky.freqs):
+            ad, as_, dbd, dtd, dbs = O.sed(nu, bd, td, bs)
+            a = (1.0, ad, as_)
+            for s in range(2):
+                w = sky.ninv[s, n]
+                for j, (der, col) in enumerate(((dbd, 1), (dtd, 1), (dbs, 2))):
+                    k = off[j] + lab[j, p]
+                    terms = [-2.0 * w * der * sh[s, col] * d[s, n, p]]
+                    terms += [2.0 * w * der * sh[s, col] * a[i] * sh[s, i] for i in range(3)]
+                    signed[k] += sum(terms)
+                    mags[k] += sum(abs(t) for t in terms)
+    assert np.allclose(signed, g, rtol=1e-10, atol=1e-12 * np.max(np.abs(g)))
+    assert np.allclose(gt, mags, rtol=1e-13, atol=0)
+    assert np.all(gt >= ga * (1 - 1e-14)) and np.all(ga >= np.abs(g) * (1 - 1e-14))
+
+
 # --------------------------------------------------------------------------------------------
 # invariants of the spectral likelihood
 # --------------------------------------------------------------------------------------------

@@ -68,6 +68,7 @@ typedef enum { CS_NINV_BAND = 0, CS_NINV_PIXEL = 1 } cs_ninv_mode;
 #define CS_ITEM_LS_FAIL 4    /* optimiser: line search exhausted its backtracks           */
 #define CS_ITEM_MAXITER 8    /* optimiser: iteration limit reached                        */
 #define CS_ITEM_CONVERGED 16 /* optimiser: projected-gradient tolerance reached           */
+#define CS_ITEM_RUNNING 32   /* optimiser: paused by the caller's replay limit (resumable)  */
 
 typedef struct {
     int32_t nfreq;  /* F, 1..32                                                         */
@@ -203,7 +204,13 @@ cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const u
  *                      nearest bound (which is then pinned), backtracking line search
  * Defaults: solver = L-BFGS, m = 10, gtol_rel = 1e-8, max_iter = 1000, iters_per_graph = 8,
  * max_backtracks = 30, c1 = 1e-4, fp64_polish = 1, lr = 0.01, beta1 = 0.9, beta2 = 0.999,
- * eps = 1e-16, topk = 0. */
+ * eps = 1e-16, topk = 0, switch_rel = 1e-4.
+ * Mixed precision (CS_FP32_BULK with fp64_polish): the FP32-accumulation phase runs until an item
+ * converges, reaches |P g|_2 <= switch_rel |P g_0|_2, fails its line search or spends max_iter
+ * iterations; every such item that has not converged then continues from its point, with its
+ * curvature pairs, in FP64 accumulation on the same FP32 data, with max_iter more iterations.  The
+ * FP32 gradient carries a rounding error of order F u times the magnitude of its terms, which near
+ * the optimum is far above 1e-8 |P g_0|, so the last decades need the FP64 sums. */
 #define CS_SOLVER_LBFGS 0
 #define CS_SOLVER_ADATOPK 1
 typedef struct {
@@ -221,6 +228,9 @@ typedef struct {
     double eps;              /* AdaTopK: AdaBelief epsilon, >= 0                             */
     double topk;             /* AdaTopK: fraction in [0, 1] of the releasable bounds freed per
                                 iteration (at least one)                                     */
+    double switch_rel;       /* mixed precision: leave the FP32 phase at |P g|_2 <= switch_rel
+                                |P g_0|_2, in [0, 1) (0 = only on a line-search failure or the
+                                iteration limit)                                             */
 } cs_optim_opts;
 
 cs_status cs_optim_default_opts(cs_optim_opts *opts); /* host */
@@ -237,6 +247,39 @@ cs_status cs_optimize_batch(cs_problem *prob, const cs_optim_opts *opts, const d
                             const double *upper, double *x, double *f, int32_t *iters,
                             int32_t *status, int64_t *nevals, void *opt_workspace, size_t opt_bytes,
                             void *stream);
+
+/* The optimiser in resumable steps (paper Sec. 3.1: a campaign's batches are checkpointed and
+ * resumed).  As cs_optimize_batch, and:
+ *   resume       0 = start from x; 1 = continue from the state held in opt_workspace, left there
+ *                by an earlier call on a problem of the same shape (items, parameter counts,
+ *                precision) with the same opts.m and opts.solver; x is then output only.
+ *   max_replays  0 = run until every item has stopped; n > 0 = return after at most n graph
+ *                replays (n * iters_per_graph evaluation steps).  Items still running then carry
+ *                CS_ITEM_RUNNING, and x, f, iters and nevals describe their current point.
+ *   running      host, nullable: number of items still running on return.
+ * Whenever the call returns, the first cs_optimizer_workspace_bytes bytes of opt_workspace hold
+ * the optimiser's complete state (no pointers): a byte copy of them is a checkpoint, and copying
+ * it back into a 256-byte aligned workspace -- in this or another process, for a problem prepared
+ * from the same inputs -- and calling with resume = 1 continues the run.  With the same schedule the
+ * result is bit for bit that of an uninterrupted run.  Returns CS_E_STATE when the workspace does
+ * not hold a state of this shape, m, solver and precision.  Synchronises the stream. */
+cs_status cs_optimize_batch_run(cs_problem *prob, const cs_optim_opts *opts, const double *lower,
+                                const double *upper, double *x, double *f, int32_t *iters,
+                                int32_t *status, int64_t *nevals, void *opt_workspace,
+                                size_t opt_bytes, int32_t resume, int32_t max_replays,
+                                int32_t *running, void *stream);
+
+/* Contiguous item chunking (paper Sec. 3.1: worker k of P takes the items
+ * [floor(k N / P), floor((k + 1) N / P))).  host outputs; 0 <= rank < nranks, nitems >= 0. */
+cs_status cs_item_range(int32_t rank, int32_t nranks, int32_t nitems, int32_t *begin, int32_t *end);
+
+/* *out = the descriptor of items [begin, end) of *in (0 <= begin < end <= in->nitems): the item
+ * arrays (d, per-pixel N^-1, labels, nclusters) are offset by their item strides; arrays shared
+ * by all items (stride 0) stay shared.  No copy is made: *out points into *in's arrays, which must
+ * outlive it.  A problem created from each chunk gives bit for bit the results of those items in
+ * the whole batch. */
+cs_status cs_problem_desc_slice(const cs_problem_desc *in, int32_t begin, int32_t end,
+                                cs_problem_desc *out);
 
 /* Launch schedule of the per-pixel kernel (chosen by cs_problem_autotune or set by hand). */
 typedef struct {

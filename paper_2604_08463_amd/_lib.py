@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcs.so")
 
 CS_OK, CS_E_INVALID, CS_E_LABEL, CS_E_WORKSPACE, CS_E_HIP, CS_E_UNSUPPORTED, CS_E_STATE = range(7)
 PRECISION = {"fp64": 0, "fp32_bulk": 1, "fp32_store": 2}
-NOT_PD, NONFINITE, LS_FAIL, MAXITER, CONVERGED = 1, 2, 4, 8, 16
+NOT_PD, NONFINITE, LS_FAIL, MAXITER, CONVERGED, RUNNING = 1, 2, 4, 8, 16, 32
 
 
 class CsError(RuntimeError):
@@ -47,7 +47,7 @@ class OptimOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("gtol_rel", C.c_double), ("max_iter", C.c_int32), ("iters_per_graph", C.c_int32),
                 ("max_backtracks", C.c_int32), ("c1", C.c_double), ("fp64_polish", C.c_int32),
                 ("solver", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
-                ("eps", C.c_double), ("topk", C.c_double)]
+                ("eps", C.c_double), ("topk", C.c_double), ("switch_rel", C.c_double)]
 
 
 SOLVER_LBFGS, SOLVER_ADATOPK = 0, 1
@@ -64,7 +64,8 @@ EXPORTS = [
     "cs_problem_create", "cs_problem_param_offsets", "cs_problem_workspace_bytes", "cs_problem_prepare",
     "cs_problem_item_info", "cs_problem_segments", "cs_likelihood", "cs_likelihood_grad", "cs_component_maps",
     "cs_kmeans_workspace_bytes", "cs_kmeans_batch", "cs_optim_default_opts",
-    "cs_optimizer_workspace_bytes", "cs_optimize_batch", "cs_problem_get_schedule", "cs_problem_set_schedule",
+    "cs_optimizer_workspace_bytes", "cs_optimize_batch", "cs_optimize_batch_run", "cs_item_range",
+    "cs_problem_desc_slice", "cs_problem_get_schedule", "cs_problem_set_schedule",
     "cs_problem_autotune", "cs_problem_set_timing", "cs_problem_kernel_time", "cs_problem_destroy", "cs_status_str",
     "cs_last_error",
 ]
@@ -94,6 +95,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.cs_optim_default_opts.argtypes = [P(OptimOpts)]
     L.cs_optimizer_workspace_bytes.argtypes = [vp, i32, P(C.c_size_t)]
     L.cs_optimize_batch.argtypes = [vp, P(OptimOpts), vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    L.cs_optimize_batch_run.argtypes = [vp, P(OptimOpts), vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, i32, i32, P(i32),
+                                        vp]
+    L.cs_item_range.argtypes = [i32, i32, i32, P(i32), P(i32)]
+    L.cs_problem_desc_slice.argtypes = [P(Desc), i32, i32, P(Desc)]
     L.cs_problem_get_schedule.argtypes = [vp, P(Schedule)]
     L.cs_problem_set_schedule.argtypes = [vp, P(Schedule)]
     L.cs_problem_autotune.argtypes = [vp, vp, vp, vp, i32, P(Schedule), vp]
@@ -139,6 +144,38 @@ def default_opts(**kw) -> OptimOpts:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def item_range(rank: int, nranks: int, nitems: int) -> tuple[int, int]:
+    """Items ``[begin, end)`` of worker ``rank`` of ``nranks`` (contiguous chunking)."""
+    b, e = C.c_int32(), C.c_int32()
+    _check(load().cs_item_range(rank, nranks, nitems, C.byref(b), C.byref(e)), "cs_item_range")
+    return b.value, e.value
+
+
+class OptState:
+    """The optimiser workspace of one problem: the complete, resumable state of a batched run
+    (256-byte aligned view of a device buffer).  ``to_host()`` copies it out (a checkpoint);
+    ``from_host()`` puts a checkpoint into a fresh workspace."""
+
+    def __init__(self, nbytes: int, device):
+        self.nbytes = nbytes
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._off = (-self._buf.data_ptr()) % 256
+        self.view = self._buf[self._off:self._off + nbytes]
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.view.data_ptr())
+
+    def to_host(self) -> np.ndarray:
+        return self.view.cpu().numpy().copy()
+
+    @classmethod
+    def from_host(cls, data: np.ndarray, device) -> "OptState":
+        st = cls(int(data.size), device)
+        st.view.copy_(torch.from_numpy(np.ascontiguousarray(data, dtype=np.uint8)))
+        return st
 
 
 def kmeans_batch(vecs: torch.Tensor, k, init: torch.Tensor, keep: torch.Tensor | None = None, iters: int = 20,
@@ -227,6 +264,14 @@ class Problem:
         desc.labels_item_stride = 0 if labels.shape[0] == 1 else 3 * P
         self._ncl = ncl
         desc.nclusters = ncl.ctypes.data_as(C.POINTER(C.c_int32))
+        self._setup(desc, d.device, precision, stream)
+
+    def _setup(self, desc, dev, precision, stream):
+        """Creates and prepares the library problem of a filled descriptor."""
+        L = load()
+        self._desc = desc
+        B, F, P = desc.nitems, desc.nfreq, desc.npix
+        ncl = np.ctypeslib.as_array(desc.nclusters, shape=(B, 3)).copy()
         h = C.c_void_p()
         _check(L.cs_problem_create(C.byref(desc), C.byref(h)), "cs_problem_create")
         self._h = h
@@ -238,7 +283,6 @@ class Problem:
         nb = C.c_size_t()
         _check(L.cs_problem_workspace_bytes(h, C.byref(nb)), "cs_problem_workspace_bytes")
         self.workspace_bytes = nb.value
-        dev = d.device
         self.device = dev
         self._ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
         base = self._ws.data_ptr()
@@ -246,6 +290,20 @@ class Problem:
         self._stream = stream
         _check(L.cs_problem_prepare(h, self._ws_ptr, nb.value, _stream(stream)), "cs_problem_prepare")
         self.param_item = torch.as_tensor(np.repeat(np.arange(B), np.diff(off)), device=dev)
+
+    def chunk(self, rank: int, nranks: int, stream=None) -> "Problem":
+        """A problem over this batch's items of worker ``rank`` of ``nranks`` (contiguous chunking,
+        the same device arrays, no copy): ``cs_item_range`` then ``cs_problem_desc_slice``."""
+        b, e = item_range(rank, nranks, self.nitems)
+        out = Desc()
+        _check(load().cs_problem_desc_slice(C.byref(self._desc), b, e, C.byref(out)), "cs_problem_desc_slice")
+        sub = Problem.__new__(Problem)
+        # the arrays the sliced descriptor points into
+        sub._keep = list(self._keep)
+        sub.freqs, sub._ncl, sub._ninv = self.freqs, self._ncl, getattr(self, "_ninv", None)
+        sub._setup(out, self.device, self.precision, stream)
+        sub.item_begin = b
+        return sub
 
     @classmethod
     def from_sky(cls, sky, precision: str = "fp64", device="cuda", d_dtype=torch.float64, **kw):
@@ -321,23 +379,33 @@ class Problem:
                "cs_component_maps")
         return m, v, st
 
-    def cs_optimize_batch(self, lower, upper, x0, opts: OptimOpts | None = None):
+    def optimizer_state(self, m: int = 10) -> OptState:
+        nb = C.c_size_t()
+        _check(load().cs_optimizer_workspace_bytes(self._h, m, C.byref(nb)), "cs_optimizer_workspace_bytes")
+        return OptState(nb.value, self.device)
+
+    def cs_optimize_batch(self, lower, upper, x0, opts: OptimOpts | None = None, *, state: OptState | None = None,
+                          resume: bool = False, max_replays: int = 0):
+        """Batched bounded minimisation.  Without ``state`` a fresh workspace is used; with it
+        the run keeps its state there, ``resume=True`` continues a run held in it, and
+        ``max_replays > 0`` pauses after that many graph replays (items still running carry
+        ``RUNNING``).  Returns ``dict(x, f, iters, status, nevals, running, state)``."""
         L = load()
         o = opts if opts is not None else default_opts()
         lo, hi = self._x(lower), self._x(upper)
-        x = self._x(x0).clone()
+        x = self._x(x0).clone() if x0 is not None else torch.empty(self.nparams, dtype=torch.float64,
+                                                                   device=self.device)
         B = self.nitems
         f = torch.empty(B, dtype=torch.float64, device=self.device)
         it = torch.empty(B, dtype=torch.int32, device=self.device)
         st = torch.empty(B, dtype=torch.int32, device=self.device)
         ne = torch.empty(B, dtype=torch.int64, device=self.device)
-        nb = C.c_size_t()
-        _check(L.cs_optimizer_workspace_bytes(self._h, o.m, C.byref(nb)), "cs_optimizer_workspace_bytes")
-        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
-        wp = C.c_void_p((ws.data_ptr() + 255) & ~255)
-        _check(L.cs_optimize_batch(self._h, C.byref(o), _ptr(lo), _ptr(hi), _ptr(x), _ptr(f), _ptr(it), _ptr(st),
-                                   _ptr(ne), wp, nb.value, _stream(self._stream)), "cs_optimize_batch")
-        return dict(x=x, f=f, iters=it, status=st, nevals=ne)
+        ws = state if state is not None else self.optimizer_state(o.m)
+        running = C.c_int32(0)
+        _check(L.cs_optimize_batch_run(self._h, C.byref(o), _ptr(lo), _ptr(hi), _ptr(x), _ptr(f), _ptr(it), _ptr(st),
+                                       _ptr(ne), ws.ptr, ws.nbytes, int(resume), int(max_replays),
+                                       C.byref(running), _stream(self._stream)), "cs_optimize_batch_run")
+        return dict(x=x, f=f, iters=it, status=st, nevals=ne, running=running.value, state=ws)
 
     def get_schedule(self) -> Schedule:
         s = Schedule()

@@ -431,6 +431,7 @@ cs_status cs_optim_default_opts(cs_optim_opts *o) {
     o->beta2 = 0.999;
     o->eps = 1e-16;
     o->topk = 0.0;
+    o->switch_rel = 1e-4;
     return CS_OK;
 }
 
@@ -440,13 +441,18 @@ cs_status cs_optimizer_workspace_bytes(const cs_problem *p, int32_t m, size_t *b
     return CS_OK;
 }
 
-cs_status cs_optimize_batch(cs_problem *p, const cs_optim_opts *o, const double *lower, const double *upper,
-                            double *x, double *f, int32_t *iters, int32_t *status, int64_t *nevals,
-                            void *opt_workspace, size_t opt_bytes, void *stream) {
+cs_status cs_optimize_batch_run(cs_problem *p, const cs_optim_opts *o, const double *lower, const double *upper,
+                                double *x, double *f, int32_t *iters, int32_t *status, int64_t *nevals,
+                                void *opt_workspace, size_t opt_bytes, int32_t resume, int32_t max_replays,
+                                int32_t *running, void *stream) {
+    if (running) *running = 0;
     if (!p || !o || !lower || !upper || !x || !f || !iters || !status) return invalid("null argument");
     if (o->m < 1 || o->m > 32 || o->max_iter < 0 || o->iters_per_graph < 1 || o->iters_per_graph > 4096 ||
-        o->max_backtracks < 0 || !(o->c1 > 0.0 && o->c1 < 1.0) || !(o->gtol_rel >= 0.0))
+        o->max_backtracks < 0 || !(o->c1 > 0.0 && o->c1 < 1.0) || !(o->gtol_rel >= 0.0) ||
+        !(o->switch_rel >= 0.0 && o->switch_rel < 1.0))
         return invalid("bad optimiser options");
+    if (resume != 0 && resume != 1) return invalid("resume must be 0 or 1");
+    if (max_replays < 0) return invalid("max_replays must be >= 0");
     if (o->solver != CS_SOLVER_LBFGS && o->solver != CS_SOLVER_ADATOPK) return invalid("unknown solver");
     if (o->solver == CS_SOLVER_ADATOPK &&
         (!(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) || !(o->beta2 >= 0.0 && o->beta2 < 1.0) ||
@@ -460,7 +466,37 @@ cs_status cs_optimize_batch(cs_problem *p, const cs_optim_opts *o, const double 
         set_error("optimizer workspace must be non-null and 256-byte aligned");
         return CS_E_WORKSPACE;
     }
-    return optimize(p, o, lower, upper, x, f, iters, status, nevals, opt_workspace, opt_bytes, (hipStream_t)stream);
+    return optimize(p, o, lower, upper, x, f, iters, status, nevals, opt_workspace, opt_bytes, resume, max_replays,
+                    running, (hipStream_t)stream);
+}
+
+cs_status cs_optimize_batch(cs_problem *p, const cs_optim_opts *o, const double *lower, const double *upper,
+                            double *x, double *f, int32_t *iters, int32_t *status, int64_t *nevals,
+                            void *opt_workspace, size_t opt_bytes, void *stream) {
+    return cs_optimize_batch_run(p, o, lower, upper, x, f, iters, status, nevals, opt_workspace, opt_bytes, 0, 0,
+                                 nullptr, stream);
+}
+
+cs_status cs_item_range(int32_t rank, int32_t nranks, int32_t nitems, int32_t *begin, int32_t *end) {
+    if (!begin || !end || nranks < 1 || rank < 0 || rank >= nranks || nitems < 0)
+        return invalid("cs_item_range needs 0 <= rank < nranks and nitems >= 0");
+    *begin = (int32_t)((int64_t)rank * nitems / nranks);
+    *end = (int32_t)((int64_t)(rank + 1) * nitems / nranks);
+    return CS_OK;
+}
+
+cs_status cs_problem_desc_slice(const cs_problem_desc *in, int32_t begin, int32_t end, cs_problem_desc *out) {
+    if (!in || !out || begin < 0 || end <= begin || end > in->nitems) return invalid("bad item slice");
+    const size_t elem = in->d_dtype == CS_DTYPE_F32 ? 4 : 8;
+    cs_problem_desc d = *in;
+    d.nitems = end - begin;
+    d.d = (const char *)in->d + (size_t)begin * (size_t)in->d_item_stride * elem;
+    if (in->ninv_mode == CS_NINV_PIXEL && in->ninv_pixel)
+        d.ninv_pixel = (const char *)in->ninv_pixel + (size_t)begin * (size_t)in->ninv_item_stride * elem;
+    d.labels = in->labels + (size_t)begin * (size_t)in->labels_item_stride;
+    d.nclusters = in->nclusters + 3 * (size_t)begin;
+    *out = d;
+    return CS_OK;
 }
 
 cs_status cs_problem_get_schedule(const cs_problem *p, cs_schedule *s) {

@@ -175,6 +175,6 @@ cs_status kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint
 size_t optimizer_bytes(const cs_problem *p, int32_t m);
 cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, const double *hi,
                    double *x, double *f, int32_t *iters, int32_t *status, int64_t *nevals, void *ws,
-                   size_t bytes, hipStream_t s);
+                   size_t bytes, int32_t resume, int32_t max_replays, int32_t *running, hipStream_t s);
 
 }  // namespace csi

@@ -14,6 +14,7 @@
 // bound by the sign of their gradient).  Items that finish are masked out of the evaluation
 // kernels through active[].  The host reads one counter after each replay.
 #include <algorithm>
+#include <vector>
 
 #include "cs_internal.h"
 
@@ -24,7 +25,7 @@ enum : int32_t { ST_INIT = 0, ST_REINIT = 1, ST_SEARCH = 2, ST_DONE = 3 };
 struct OptItem {
     double f, pg0, alpha, dec;
     int64_t nevals;
-    int32_t state, status, iter, nbt, npairs, newest, pad0, pad1;
+    int32_t state, status, iter, nbt, npairs, newest, iter0, pad1;  // iter0: iterations before this phase
     // AdaTopK: objective scale, bias-correction powers, last accepted step, step limit
     double scale, b1t, b2t, aprev, amax;
     int32_t t, lim, hit, pad2;
@@ -44,11 +45,13 @@ struct OptArgs {
     int64_t ktot;
     int32_t m, max_iter, max_backtracks, solver;
     double gtol, c1;
+    double gsw;  // FP32 phase of the mixed-precision run: leave it at |Pg| <= gsw |Pg_0| (0 = off)
     int32_t *piv;  // [Ktot] AdaTopK pivots: -1 lower bound, +1 upper bound, 0 free
     double lr, b1, b2, eps, topk;
 };
 
 constexpr int kOptThreads = 256;   // block size of the small per-item kernels
+constexpr int32_t kSwitch = 1 << 8;  // internal status bit: the item reached the FP32 phase's tolerance
 constexpr double kFlatRel = 1e-12;  // relative change of F below which Armijo is not resolved
 
 // deterministic block sum of N values (fixed shuffle tree, then the waves in order)
@@ -91,6 +94,15 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     for (int w = 1; w < NWV; ++w) x = fmax(x, sh[w]);
     __syncthreads();
     return x;
+}
+
+// Stopping tests after an accepted step, in order: the relative projected-gradient tolerance,
+// the switch tolerance of the FP32 phase of a mixed-precision run, the phase's iteration budget.
+__device__ __forceinline__ int32_t stop_test(const OptArgs &a, const OptItem &s, double pgn) {
+    if (pgn <= a.gtol * s.pg0) return CS_ITEM_CONVERGED;
+    if (pgn <= a.gsw * s.pg0) return kSwitch;
+    if (s.iter - s.iter0 >= a.max_iter) return CS_ITEM_MAXITER;
+    return 0;
 }
 
 __device__ __forceinline__ bool is_free(double y, double g) {
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
                 else if (s.pg0 == 0.0)
                     finish = CS_ITEM_CONVERGED;
             }
-            if (!finish && s.iter >= a.max_iter) finish = CS_ITEM_MAXITER;
+            if (!finish && s.iter - s.iter0 >= a.max_iter) finish = CS_ITEM_MAXITER;
             need_dir = !finish;
         }
     } else if (s.state == ST_SEARCH) {
@@ -208,10 +220,7 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
             }
             s.f = fe;
             s.iter += 1;
-            if (sqrt(pg[0]) <= a.gtol * s.pg0)
-                finish = CS_ITEM_CONVERGED;
-            else if (s.iter >= a.max_iter)
-                finish = CS_ITEM_MAXITER;
+            finish = stop_test(a, s, sqrt(pg[0]));
             need_dir = !finish;
         } else {
             s.nbt += 1;
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
                 else if (s.pg0 == 0.0)
                     finish = CS_ITEM_CONVERGED;
             }
-            if (!finish && s.iter >= a.max_iter) finish = CS_ITEM_MAXITER;
+            if (!finish && s.iter - s.iter0 >= a.max_iter) finish = CS_ITEM_MAXITER;
             need_dir = !finish;
         }
     } else if (s.state == ST_SEARCH) {
@@ -465,10 +474,7 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             }
             s.f = fe;
             s.iter += 1;
-            if (sqrt(pg[0]) <= a.gtol * s.pg0)
-                finish = CS_ITEM_CONVERGED;
-            else if (s.iter >= a.max_iter)
-                finish = CS_ITEM_MAXITER;
+            finish = stop_test(a, s, sqrt(pg[0]));
             need_dir = !finish;
         } else {
             s.nbt += 1;
@@ -840,14 +846,8 @@ __global__ __launch_bounds__(NT) void k_ada_update(OptArgs a) {
                 break;
             }
         }
-        if (pgn <= a.gtol * s.pg0) {
-            finish = CS_ITEM_CONVERGED;
-            break;
-        }
-        if (s.iter >= a.max_iter) {
-            finish = CS_ITEM_MAXITER;
-            break;
-        }
+        finish = stop_test(a, s, pgn);
+        if (finish) break;
         s.state = ST_SEARCH;  // any later pass of this loop is a continuation
         // 3. rescaling of the objective scale and the moments
         const double cpg = s.scale * pgn;
@@ -931,11 +931,16 @@ __global__ __launch_bounds__(NT) void k_ada_update(OptArgs a) {
     }
 }
 
-// items stopped by a line-search failure continue from their point (pairs kept) in FP64
-__global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t nitems) {
+// Start of the FP64-accumulation phase of a mixed-precision run: every item that stopped in the
+// FP32 phase for a reason other than convergence or a bad evaluation (its line search failed, it
+// reached the switch tolerance or spent the phase's iteration budget) continues from its point with
+// its curvature pairs and a fresh budget.
+__global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a) {
     const int item = blockIdx.x;
     OptItem *s = a.st + item;
-    if (!(s->state == ST_DONE && (s->status & CS_ITEM_LS_FAIL))) return;
+    constexpr int32_t kResume = CS_ITEM_LS_FAIL | CS_ITEM_MAXITER | kSwitch;
+    if (!(s->state == ST_DONE && (s->status & kResume) && !(s->status & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE))))
+        return;
     const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
     for (int64_t i = threadIdx.x; i < K; i += blockDim.x) {
         a.yt[o + i] = a.y[o + i];
@@ -943,24 +948,35 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_repolish(OptArgs a, int32_t
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        s->status &= ~CS_ITEM_LS_FAIL;
+        s->status &= ~kResume;
         s->state = ST_REINIT;
+        s->iter0 = s->iter;
         a.active[item] = 1;
         atomicAdd(a.nactive, 1);
     }
-    (void)nitems;
 }
 
+// x, f, iters, status and nevals of every item.  An item still running carries CS_ITEM_RUNNING when
+// the caller's replay limit stopped the run (paused), else CS_ITEM_MAXITER (the replay bound).  When
+// the run is paused before its FP64-accumulation phase (polish_pending), an item that has left the
+// FP32 phase without converging will continue too, and is reported running.
 __global__ __launch_bounds__(kOptThreads) void k_opt_output(OptArgs a, double *x, double *f, int32_t *iters,
-                                                            int32_t *status, int64_t *nevals) {
+                                                            int32_t *status, int64_t *nevals, int32_t paused,
+                                                            int32_t polish_pending) {
     const int item = blockIdx.x;
     OptItem s = a.st[item];
     const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
     for (int64_t i = threadIdx.x; i < K; i += blockDim.x)
         x[o + i] = a.lo[o + i] + a.y[o + i] * (a.hi[o + i] - a.lo[o + i]);
     if (threadIdx.x == 0) {
+        constexpr int32_t kResume = CS_ITEM_LS_FAIL | CS_ITEM_MAXITER | kSwitch;
         int32_t stt = s.status;
-        if (s.state != ST_DONE) stt |= CS_ITEM_MAXITER;  // stopped by the replay cap
+        if (s.state != ST_DONE) {
+            stt |= paused ? CS_ITEM_RUNNING : CS_ITEM_MAXITER;
+        } else if (polish_pending && (stt & kResume) && !(stt & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE))) {
+            stt = (stt & ~kResume) | CS_ITEM_RUNNING;
+        }
+        stt &= ~kSwitch;
         f[item] = s.f;
         iters[item] = s.iter;
         status[item] = stt;
@@ -973,9 +989,22 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_output(OptArgs a, double *x
 // ---------------------------------------------------------------------------------------------
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// First record of the optimiser workspace: what the state belongs to and how far the run is.  The
+// rest of the workspace (per-item records, vectors, curvature pairs) holds no pointers, so a byte
+// copy of the workspace is a complete checkpoint.
+struct OptHeader {
+    uint64_t magic;
+    int64_t ktot;
+    int32_t nitems, m, solver, precision;
+    int32_t phase;   // 0: first (working-precision) phase; 1: FP64-accumulation phase started
+    int32_t phases;  // 1, or 2 for a mixed-precision run
+    int64_t replays; // graph replays so far (all calls)
+};
+constexpr uint64_t kOptMagic = 0x6373306f70743031ull;  // state format 1
+
 size_t optimizer_bytes(const cs_problem *p, int32_t m) {
     const size_t B = (size_t)p->B, K = (size_t)p->xoff[p->B];
-    size_t t = 0;
+    size_t t = al256(sizeof(OptHeader));
     t += al256(sizeof(OptItem) * B);
     t += al256(sizeof(int32_t) * B) * 2 + al256(sizeof(int32_t));
     t += al256(sizeof(double) * B);
@@ -986,7 +1015,8 @@ size_t optimizer_bytes(const cs_problem *p, int32_t m) {
 }
 
 cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, const double *hi, double *x, double *f,
-                   int32_t *iters, int32_t *status, int64_t *nevals, void *ws, size_t bytes, hipStream_t caller) {
+                   int32_t *iters, int32_t *status, int64_t *nevals, void *ws, size_t bytes, int32_t resume,
+                   int32_t max_replays, int32_t *running, hipStream_t caller) {
     const int B = p->B;
     const int64_t K = p->xoff[B];
     int64_t kmax = 0;
@@ -1002,6 +1032,7 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
         off += al256(n);
         return r;
     };
+    OptHeader *hdr_dev = (OptHeader *)take(sizeof(OptHeader));
     OptArgs a;
     a.st = (OptItem *)take(sizeof(OptItem) * B);
     a.active = (int32_t *)take(sizeof(int32_t) * B);
@@ -1035,41 +1066,69 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
     a.b2 = o->beta2;
     a.eps = o->eps;
     a.topk = o->topk;
+    const int phases = (p->prec == CS_FP32_BULK && o->fp64_polish) ? 2 : 1;
 
     CSI_HIP(hipStreamSynchronize(caller));
+    OptHeader hdr{};
+    if (resume) {
+        CSI_HIP(hipMemcpy(&hdr, hdr_dev, sizeof hdr, hipMemcpyDeviceToHost));
+        if (hdr.magic != kOptMagic || hdr.ktot != K || hdr.nitems != B || hdr.m != o->m || hdr.solver != o->solver ||
+            hdr.precision != (int32_t)p->prec || hdr.phases != phases || hdr.phase < 0 || hdr.phase >= phases) {
+            set_error("optimizer workspace does not hold a state of this problem shape, m, solver and precision");
+            return CS_E_STATE;
+        }
+    } else {
+        hdr.magic = kOptMagic;
+        hdr.ktot = K;
+        hdr.nitems = B;
+        hdr.m = o->m;
+        hdr.solver = o->solver;
+        hdr.precision = (int32_t)p->prec;
+        hdr.phase = 0;
+        hdr.phases = phases;
+        hdr.replays = 0;
+    }
     hipStream_t s;
     CSI_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     cs_status rc = CS_OK;
     const bool was_timing = p->timing;
     p->timing = false;  // no event records inside captured graphs
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
     int32_t *hcount = nullptr;
+    int32_t nrun = 0;
+    bool paused = false;
     do {
-        hipLaunchKernelGGL(k_opt_init, dim3(B), dim3(kOptThreads), 0, s, a, x, B);
-        hipError_t e0 = hipGetLastError();
-        if (e0 != hipSuccess) {
-            rc = hip_fail(e0, "k_opt_init");
-            break;
-        }
         hipError_t eh = hipHostMalloc((void **)&hcount, sizeof(int32_t), hipHostMallocDefault);
         if (eh != hipSuccess) {
             hcount = nullptr;
             rc = hip_fail(eh, "hipHostMalloc");
             break;
         }
-        const int phases = (p->prec == CS_FP32_BULK && o->fp64_polish) ? 2 : 1;
-        // bound on replays: every item needs at most max_iter * (max_backtracks + 1) + 1 evaluations
+        if (!resume) {
+            hipLaunchKernelGGL(k_opt_init, dim3(B), dim3(kOptThreads), 0, s, a, x, B);
+            hipError_t e0 = hipGetLastError();
+            if (e0 != hipSuccess) {
+                rc = hip_fail(e0, "k_opt_init");
+                break;
+            }
+        }
+        // bound on replays of one call: every item needs at most max_iter * (max_backtracks + 1) + 1
+        // evaluations per phase
         const int64_t max_steps = (int64_t)(o->max_iter + 1) * (o->max_backtracks + 1) + 2;
-        for (int ph = 0; ph < phases && rc == CS_OK; ++ph) {
+        int64_t replays_left = max_replays > 0 ? max_replays : INT64_MAX;
+        for (int ph = hdr.phase; ph < phases && rc == CS_OK; ++ph) {
             const cs_precision mode = (ph == 0) ? p->prec : CS_FP32_STORE;
-            if (ph == 1) {
-                hipLaunchKernelGGL(k_opt_repolish, dim3(B), dim3(kOptThreads), 0, s, a, B);
+            a.gsw = (phases == 2 && ph == 0) ? o->switch_rel : 0.0;
+            if (ph > hdr.phase) {
+                // entering the FP64-accumulation phase (not when resuming inside it)
+                hipLaunchKernelGGL(k_opt_repolish, dim3(B), dim3(kOptThreads), 0, s, a);
                 hipError_t e3 = hipGetLastError();
                 if (e3 != hipSuccess) {
                     rc = hip_fail(e3, "k_opt_repolish");
                     break;
                 }
+                hdr.phase = ph;
             }
             hipError_t ecap = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (ecap != hipSuccess) {
@@ -1093,20 +1152,31 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
                     if (eu != hipSuccess) rc = hip_fail(eu, "k_opt_update");
                 }
             }
-            hipError_t ec = hipStreamEndCapture(s, &graph[ph]);
+            hipError_t ec = hipStreamEndCapture(s, &graph);
             if (rc != CS_OK) break;
             if (ec != hipSuccess) {
                 rc = hip_fail(ec, "hipStreamEndCapture");
                 break;
             }
-            ec = hipGraphInstantiate(&exec[ph], graph[ph], nullptr, nullptr, 0);
+            ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (ec != hipSuccess) {
                 rc = hip_fail(ec, "hipGraphInstantiate");
                 break;
             }
+            // the active count of a resumed run decides whether its phase still has work
+            ec = hipMemcpyAsync(hcount, a.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (ec == hipSuccess) ec = hipStreamSynchronize(s);
+            if (ec != hipSuccess) {
+                rc = hip_fail(ec, "optimizer state read");
+                break;
+            }
             int64_t steps = 0;
-            for (;;) {
-                hipError_t e1 = hipGraphLaunch(exec[ph], s);
+            while (*hcount > 0 && steps < max_steps) {
+                if (replays_left <= 0) {
+                    paused = true;
+                    break;
+                }
+                hipError_t e1 = hipGraphLaunch(exec, s);
                 if (e1 == hipSuccess) e1 = hipMemcpyAsync(hcount, a.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
                 if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
                 if (e1 != hipSuccess) {
@@ -1114,22 +1184,38 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
                     break;
                 }
                 steps += o->iters_per_graph;
-                if (*hcount <= 0 || steps >= max_steps) break;
+                --replays_left;
+                ++hdr.replays;
             }
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+            if (paused) break;
         }
         if (rc != CS_OK) break;
-        hipLaunchKernelGGL(k_opt_output, dim3(B), dim3(kOptThreads), 0, s, a, x, f, iters, status, nevals);
-        hipError_t e2 = hipGetLastError();
+        const int32_t polish_pending = paused && hdr.phase + 1 < phases;
+        hipError_t e2 = hipMemcpyAsync(hdr_dev, &hdr, sizeof hdr, hipMemcpyHostToDevice, s);
+        if (e2 == hipSuccess) {
+            hipLaunchKernelGGL(k_opt_output, dim3(B), dim3(kOptThreads), 0, s, a, x, f, iters, status, nevals,
+                               (int32_t)paused, polish_pending);
+            e2 = hipGetLastError();
+        }
+        std::vector<int32_t> hst;
+        if (e2 == hipSuccess && paused) {  // items reported running, for the caller's count
+            hst.resize(B);
+            e2 = hipMemcpyAsync(hst.data(), status, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s);
+        }
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
         if (e2 != hipSuccess) rc = hip_fail(e2, "k_opt_output");
+        for (int32_t v : hst) nrun += (v & CS_ITEM_RUNNING) ? 1 : 0;
     } while (false);
-    for (int ph = 0; ph < 2; ++ph) {
-        if (exec[ph]) (void)hipGraphExecDestroy(exec[ph]);
-        if (graph[ph]) (void)hipGraphDestroy(graph[ph]);
-    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (hcount) (void)hipHostFree(hcount);
     (void)hipStreamDestroy(s);
     p->timing = was_timing;
+    if (running) *running = nrun;
     return rc;
 }
 

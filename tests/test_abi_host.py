@@ -149,3 +149,45 @@ def test_schedule_validation(lib):
     assert lib.cs_problem_get_schedule(h, C.byref(g)) == 0
     assert (g.waves_per_block, g.blocks_per_cu, g.xcd_remap) == (8, 4, 0)
     lib.cs_problem_destroy(h)
+
+
+def test_optimizer_switch_default(lib):
+    o = _lib.OptimOpts()
+    assert lib.cs_optim_default_opts(C.byref(o)) == 0
+    assert o.switch_rel == 1e-4
+
+
+@pytest.mark.parametrize("nitems,nranks", [(64, 8), (1024, 7), (5, 3), (3, 5), (0, 2), (1, 1)])
+def test_item_range_is_contiguous_floor_chunking(lib, nitems, nranks):
+    # worker k takes [floor(k N / P), floor((k+1) N / P)): the ranges tile [0, N) in order
+    ends = []
+    for k in range(nranks):
+        b, e = C.c_int32(), C.c_int32()
+        assert lib.cs_item_range(k, nranks, nitems, C.byref(b), C.byref(e)) == 0
+        assert (b.value, e.value) == ((k * nitems) // nranks, ((k + 1) * nitems) // nranks)
+        ends.append((b.value, e.value))
+    assert ends[0][0] == 0 and ends[-1][1] == nitems
+    assert all(ends[i][1] == ends[i + 1][0] for i in range(nranks - 1))
+    b, e = C.c_int32(), C.c_int32()
+    assert lib.cs_item_range(nranks, nranks, nitems, C.byref(b), C.byref(e)) == _lib.CS_E_INVALID
+
+
+def test_descriptor_slice_offsets_item_arrays(lib):
+    F, P, B = 15, 100, 6
+    d, (freqs, ninv, ncl) = _desc(F=F, P=P, B=B)
+    ncl[:] = np.arange(3 * B, dtype=np.int32).reshape(B, 3) + 1
+    d.labels_item_stride = 3 * P
+    d.d_dtype = 1  # FP32: 4-byte elements
+    out = _lib.Desc()
+    assert lib.cs_problem_desc_slice(C.byref(d), 2, 5, C.byref(out)) == 0
+    assert out.nitems == 3 and out.nfreq == F and out.npix == P
+    assert out.d == 0x1000 + 2 * (2 * F * P) * 4
+    assert out.labels == 0x2000 + 2 * 3 * P * 4
+    got = np.ctypeslib.as_array(out.nclusters, shape=(3, 3))
+    assert np.array_equal(got, ncl[2:5])
+    # shared arrays (stride 0) stay shared
+    d.d_item_stride = 0
+    assert lib.cs_problem_desc_slice(C.byref(d), 1, 2, C.byref(out)) == 0
+    assert out.d == 0x1000
+    for b, e in ((0, 0), (3, 2), (-1, 2), (4, 7)):
+        assert lib.cs_problem_desc_slice(C.byref(d), b, e, C.byref(out)) == _lib.CS_E_INVALID

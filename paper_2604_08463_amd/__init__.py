@@ -10,11 +10,14 @@ from ._lib import (  # noqa: F401
     MAXITER,
     NONFINITE,
     NOT_PD,
+    RUNNING,
     SOLVER_ADATOPK,
     SOLVER_LBFGS,
     CsError,
+    OptState,
     Problem,
     default_opts,
+    item_range,
     kmeans_batch,
     load,
 )

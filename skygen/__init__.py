@@ -8,13 +8,14 @@ part of the likelihood or of the mixing-matrix code used by either the oracle or
 from .sky import (  # noqa: F401
     BOUNDS,
     X0,
+    ScanTasks,
     Sky,
     bands,
-    chunk_bounds,
     kcap_labels,
     latitude_mask,
     make_config,
     make_tiny,
+    scan_tasks,
     sky_sed_dust,
     sky_sed_sync,
     spherical_kmeans,

@@ -189,11 +189,6 @@ def latitude_mask(z: np.ndarray, fsky: float) -> np.ndarray:
     return keep
 
 
-def chunk_bounds(rank: int, ngrid: int, nproc: int) -> tuple[int, int]:
-    """Contiguous grid slice of a rank: ``[floor(k N / P), floor((k+1) N / P))`` (Sec. 3.1)."""
-    return (rank * ngrid) // nproc, ((rank + 1) * ngrid) // nproc
-
-
 # ----------------------------------------------------------------------------------------------
 # sky
 # ----------------------------------------------------------------------------------------------
@@ -419,11 +414,7 @@ def make_config(cid: int, *, npix: int | None = None, nitems: int | None = None,
 
     # workload 4: cluster-configuration scan on the shared workload-1 data
     d = sig_t.unsqueeze(0) + _noise(sky_id, sigma, 1, P, device)
-    g = _rng(cid, "kcounts")
-    kd = g.integers(10, kmax4[0] + 1, B)
-    kt = g.integers(1, kmax4[1] + 1, B)
-    ks = g.integers(1, kmax4[2] + 1, B)
-    fsky = _rng(cid, "mask").uniform(0.4, 0.8, B)
+    kd, kt, ks, fsky = _scan_draws(cid, B, kmax4)
     labels = np.empty((B, 3, P), dtype=np.int32)
     ncl = np.empty((B, 3), dtype=np.int32)
     xs, lows, highs = [], [], []
@@ -440,6 +431,58 @@ def make_config(cid: int, *, npix: int | None = None, nitems: int | None = None,
     meta.update(k_requested=np.stack([kd, kt, ks], axis=1), fsky=fsky)
     return Sky(cid, freqs, sigma, ninv, vecs, truth, signal, d, torch.as_tensor(labels),
                ncl, xs, lows, highs, meta=meta)
+
+
+def _scan_draws(cid: int, nitems: int, kmax4: tuple):
+    """Requested cluster counts and sky fractions of the configuration scan."""
+    g = _rng(cid, "kcounts")
+    kd = g.integers(10, kmax4[0] + 1, nitems)
+    kt = g.integers(1, kmax4[1] + 1, nitems)
+    ks = g.integers(1, kmax4[2] + 1, nitems)
+    fsky = _rng(cid, "mask").uniform(0.4, 0.8, nitems)
+    return kd, kt, ks, fsky
+
+
+@dataclass
+class ScanTasks:
+    """Inputs of the configuration scan with its patchings left to be computed: one spherical
+    K-means task per (configuration c, parameter j), task t = 3 c + j.
+
+    ``keep[t]`` marks the pixels configuration c keeps (latitude cut), ``k[t]`` the requested
+    cluster count and ``init[t, :k[t]]`` (when ``k[t]`` is below the kept count) the indices, into
+    the kept pixels in ascending order, of the starting centroids -- the same seeded draws the
+    generator's own K-means uses.  ``sky`` holds the shared data (its labels and parameter points
+    are workload 1's and play no part here)."""
+
+    sky: Sky
+    keep: np.ndarray  # [3C][P] bool
+    k: np.ndarray     # [3C] int32
+    init: np.ndarray  # [3C][max k] int32
+
+    def task(self, c: int, j: int):
+        t = 3 * c + j
+        return self.keep[t], int(self.k[t]), self.init[t, :self.k[t]]
+
+
+def scan_tasks(nitems: int = 1024, kmax4: tuple = (3000, 500, 1000), device="cpu") -> ScanTasks:
+    """Workload 4's inputs for patchings computed elsewhere (e.g. on the device)."""
+    cid = 4
+    base = make_config(1, nitems=1, device=device)
+    P = base.npix
+    kd, kt, ks, fsky = _scan_draws(cid, nitems, kmax4)
+    kreq = np.stack([kd, kt, ks], axis=1).astype(np.int32).reshape(-1)
+    keep = np.empty((3 * nitems, P), dtype=bool)
+    init = np.zeros((3 * nitems, int(kreq.max())), dtype=np.int32)
+    for c in range(nitems):
+        kc = latitude_mask(base.vecs[:, 2], fsky[c])
+        n = int(kc.sum())
+        for j in range(3):
+            t = 3 * c + j
+            keep[t] = kc
+            if kreq[t] < n:  # the generator's K-means draws its start the same way
+                init[t, :kreq[t]] = _rng(cid, "kmeans", c, j).choice(n, size=int(kreq[t]), replace=False)
+    base.meta.update(workload=4, items=nitems, k_requested=kreq.reshape(nitems, 3), fsky=fsky)
+    return ScanTasks(base, keep, kreq, init)
 
 
 def make_tiny(npix: int, nfreq: int, k=(1, 1, 1), *, seed: int = 0, nitems: int = 1,

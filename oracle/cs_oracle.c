@@ -468,7 +468,12 @@ int64_t orc_segments(int64_t npix, const int32_t *labels, int32_t k, int32_t *pe
  *   with gamma = s.t / t.t of the newest used pair (1 if none).  p = -(H Pg) on the free set;
  *   if p.g >= 0 or p is not finite the memory is cleared and p = -Pg.
  *   Step: alpha0 = 1, or min(1, 1/|p|_inf) when no pair was used.  Trial
- *   y(alpha) = clip(y + alpha p, 0, 1) is accepted on Armijo, F(y(a)) <= F(y) + c1 g.(y(a) - y),
+ *   y(alpha) = clip(y + alpha p, 0, 1).  The clamp can turn a descent direction into a step that
+ *   ascends (a coordinate next to a bound that p drives out of the box carries all of p.g's
+ *   descent); a trial with g.(y(a) - y) >= 0 is therefore not evaluated: unless p is already -Pg,
+ *   the memory is cleared, p = -Pg (whose clamped steps always descend) and the search restarts at
+ *   alpha0 = min(1, 1/|p|_inf) with a fresh backtrack count.  A trial is accepted on Armijo,
+ *   F(y(a)) <= F(y) + c1 g.(y(a) - y),
  *   or, where F no longer resolves the decrease, when |F(y(a)) - F(y)| <= 1e-12 |F(y)| and
  *   g(y(a)).(y(a) - y) <= 0 (a step leaving y unchanged is rejected); alpha is halved at most
  *   max_backtracks times, else LS_FAIL.
@@ -592,6 +597,7 @@ int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double 
         for (int i = 0; i < K; ++i)
             if (fabs(p[i]) > pinf) pinf = fabs(p[i]);
         double alpha = used ? 1.0 : (pinf > 1.0 ? 1.0 / pinf : 1.0);
+        int steepest = !used; /* p = -Pg */
 
         /* projected backtracking line search with the Armijo condition */
         int accepted = 0;
@@ -601,6 +607,20 @@ int orc_lbfgs(const orc_problem *pr, const double *lo, const double *hi, double 
                 double v = y[i] + alpha * p[i];
                 yt[i] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
                 dec += g[i] * (yt[i] - y[i]);
+            }
+            if (!(dec < 0.0) && !steepest) {
+                /* the clamped step does not descend: clear the memory and search along -Pg */
+                npairs = 0;
+                newest = -1;
+                steepest = 1;
+                pinf = 0.0;
+                for (int i = 0; i < K; ++i) {
+                    p[i] = fr[i] ? -g[i] : 0.0;
+                    if (fabs(p[i]) > pinf) pinf = fabs(p[i]);
+                }
+                alpha = pinf > 1.0 ? 1.0 / pinf : 1.0;
+                bt = -1;
+                continue;
             }
             st = orc_eval_internal(&o, yt, &ft, gt);
             if (st < 0) {

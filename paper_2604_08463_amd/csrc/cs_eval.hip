@@ -416,10 +416,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
 //     bands and add their partials, and one of them forms the FP64 Cholesky factor of M into the
 //     slice; every pixel then accumulates only its data-dependent sums b and h (12 FMAs per band)
 //     and reads its segment's factor;
-//   2 segment records: k_seg_rec has summed them once per segment, with the same operations in
-//     the same order as mode 0; the wavefront copies its segments' records into the slice, each
-//     pixel accumulates only b and h (12 FMAs per band from premultiplied coefficients) and forms
-//     its FP64 Cholesky factor from its segment's record.
+//   2 segment records: k_seg_rec has summed them once per segment; each pixel accumulates only
+//     b and h (the five band products and 12 FMAs per band, against 31 operations in mode 0),
+//     then reads its segment's record and forms its FP64 Cholesky factor from it.
 // Chunks with more than kStageSeg segments take the direct-gather per-pixel path.
 // ---------------------------------------------------------------------------------------------
 // Per segment: the Cholesky factor of M (inverse diagonal), G_jk and a positive-definite flag,
@@ -438,8 +437,7 @@ struct alignas(4 * sizeof(TA)) Col4 {
 };
 
 // LDS slice of one wavefront: Col4 [kStageSeg][F]; the segment-shared mode adds TA [kStageSeg][F]
-// (16-byte padded) and double [kRecFields][kStageSeg]; the record mode adds TA [kStageSeg][F] and
-// TA [kStageSeg][kRecWords]
+// (16-byte padded) and double [kRecFields][kStageSeg]
 template <typename TA>
 __host__ __device__ constexpr size_t stage_col_bytes(int F) {
     return (size_t)kStageSeg * (size_t)F * sizeof(Col4<TA>);
@@ -451,7 +449,7 @@ __host__ __device__ constexpr size_t stage_c5_bytes(int F) {
 template <typename TA, int SM>
 __host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
     return SM == 1   ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
-           : SM == 2 ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kStageSeg * kRecWords * sizeof(TA)
+           : SM == 2 ? stage_col_bytes<TA>(F)
                      : stage_col_bytes<TA>(F);
 }
 
@@ -480,11 +478,11 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
                                             char *wave_lds) {
     constexpr bool SHARED = SM == 1;  // per-segment sums formed while staging
     constexpr bool RECS = SM == 2;    // per-segment sums read from the segment records
-    constexpr bool PREMUL = SM != 0;  // staged coefficients premultiplied by the band constants
+    constexpr bool PREMUL = SHARED;   // staged coefficients premultiplied by the band constants
     // groups of kG bands in flight per lane: the segment-shared band loop is short (12 FMAs per
     // band), so it looks further ahead (measured on gfx950: 8 groups for it; 6 for per-pixel with
     // FP32 accumulation, 4 with FP64, whose registers would otherwise cost it a wavefront)
-    constexpr int kRing = SHARED ? 8 : (sizeof(TA) == 4 ? (RECS ? 6 : 6) : 4);
+    constexpr int kRing = SHARED ? 8 : (sizeof(TA) == 4 ? 6 : 4);
     constexpr int kG = 2;
     const cptr<BandDev> B = as_const(a.band);
     const int F = a.nfreq;
@@ -568,20 +566,10 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         // column writes wait only for the gathers while the ring is still in flight
         issue_ring();
         const int lbase = (hi ? F : 0) + f;
-        const int fcl = f < F ? f : F - 1;
-        const TA wl = Band<TA>::w(B, 0, fcl), ldl = Band<TA>::ld(B, fcl), lsl = Band<TA>::ls(B, fcl);
 #pragma unroll
         for (int r = 0; r < kRounds; ++r)
-            if (r < nr && f < F && 2 * r + (hi ? 1 : 0) < nseg) {
-                const TA ad = pdv[r] * btv[r];
-                if (RECS) {  // the products of the per-pixel band loop, in its order
-                    const TA cad = wl * ad, cas = wl * ssv[r];
-                    cols[2 * r * F + lbase] = Col4<TA>{cad, cas, cad * ldl, cad * dtv[r]};
-                    c5[2 * r * F + lbase] = cas * lsl;
-                } else {
-                    cols[2 * r * F + lbase] = Col4<TA>{ad, dtv[r], ssv[r], (TA)0};
-                }
-            }
+            if (r < nr && f < F && 2 * r + (hi ? 1 : 0) < nseg)
+                cols[2 * r * F + lbase] = Col4<TA>{pdv[r] * btv[r], dtv[r], ssv[r], (TA)0};
     } else if (!SHARED) {
         // columns (a_d, da_d/dT / a_d, a_s) of every (segment, band), in phases of kPh rounds of
         // the wavefront whose gathers are all issued before their first use
@@ -613,17 +601,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
 #pragma unroll
             for (int i = 0; i < kPh; ++i) {
                 const int e = e0 + lane + i * kChunk;
-                if (e < ne) {
-                    const TA ad = pdv[i] * btv[i];
-                    if (RECS) {
-                        const int f = fi[i];
-                        const TA w = Band<TA>::w(B, 0, f), cad = w * ad, cas = w * ssv[i];
-                        cols[e] = Col4<TA>{cad, cas, cad * Band<TA>::ld(B, f), cad * dtv[i]};
-                        c5[e] = cas * Band<TA>::ls(B, f);
-                    } else {
-                        cols[e] = Col4<TA>{ad, dtv[i], ssv[i], (TA)0};
-                    }
-                }
+                if (e < ne) cols[e] = Col4<TA>{pdv[i] * btv[i], dtv[i], ssv[i], (TA)0};
             }
         }
     } else {
@@ -733,11 +711,6 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             r[kG23 * kStageSeg] = P.g23;
         }
     }
-    TA *rl = (TA *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
-    if (RECS) {  // the chunk's segment records: consecutive, so one coalesced copy
-        const gptr<TA> src = as_global((const TA *)a.segrec) + (it->part_off + segbase) * (int64_t)kRecWords;
-        for (int i = lane; i < nseg * kRecWords; i += kChunk) rl[i] = src[i];
-    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -772,12 +745,14 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const TA lgd = Band<TA>::ld(B, f), lgs = Band<TA>::ls(B, f);
         const TA wad = w * ad, was = w * as;
         const TA c1 = wad * lgd, c2 = wad * dt, c3 = was * lgs;
-        A.m01 += wad;
-        A.m02 += was;
-        A.m11 = fma(wad, ad, A.m11);
-        A.m12 = fma(wad, as, A.m12);
-        A.m22 = fma(was, as, A.m22);
-        if (GRAD) {
+        if (!RECS) {  // the record mode reads M and G from its segment's record
+            A.m01 += wad;
+            A.m02 += was;
+            A.m11 = fma(wad, ad, A.m11);
+            A.m12 = fma(wad, as, A.m12);
+            A.m22 = fma(was, as, A.m22);
+        }
+        if (GRAD && !RECS) {
             A.g01 += c1;
             A.g02 += c2;
             A.g03 += c3;
@@ -819,8 +794,6 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
                     ru[r][j] = du[f * kChunk];
                 }
             }
-            // record mode: keep the coefficient reads of later slots from being hoisted here
-            if constexpr (RECS) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -841,7 +814,9 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         ok = R[kOk * kStageSeg] != 0.0;
     } else {
         const double m00 = (double)Band<TA>::wsum(B, 0);
-        const TA *R = rl + segl * kRecWords;  // record of the pixel's segment (mode 2)
+        // record of the pixel's segment (mode 2), read after the band loop: the lanes of one
+        // segment read the same 64 bytes
+        const gptr<TA> R = as_global((const TA *)a.segrec) + (it->part_off + segbase + segl) * (int64_t)kRecWords;
         const double m01 = RECS ? (double)R[0] : (double)A.m01, m02 = RECS ? (double)R[1] : (double)A.m02,
                      m11 = RECS ? (double)R[2] : (double)A.m11, m12 = RECS ? (double)R[3] : (double)A.m12,
                      m22 = RECS ? (double)R[4] : (double)A.m22;
@@ -901,7 +876,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
 // modes with FP32 accumulation (at most 96 VGPRs); the other modes are left to the compiler.
 template <typename TA, int SM>
 constexpr int stage_waves() {
-    return SM == 1 ? 1 : (sizeof(TA) == 4 ? (SM == 2 ? 4 : 5) : 1);
+    return SM == 1 ? 1 : (sizeof(TA) == 4 ? 5 : 1);
 }
 
 template <typename TS, typename TA, bool GRAD, int SM>
@@ -930,11 +905,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
 
 // ---------------------------------------------------------------------------------------------
 // Segment records (schedule mode 2): M = A^T N^-1 A (upper triangle without m00, which is the band
-// weight sum) and, for the gradient, G_jk of each segment's label triple, summed over the bands
-// with the operations and order of the per-pixel band loop.  One thread per (item, segment);
-// the record is [m01 m02 m11 m12 m22 | g01 g02 g03 g11 g12 g13 g21 g22 g23 | 0 0].
+// weight sum) and, for the gradient, G_jk of each segment's label triple.  Four lanes per (item,
+// segment): lane q of the quad sums the bands q, q + 4, ... (all its table gathers issued first),
+// then DPP quad sums combine the four partial sums (the same value in each lane) and lane q stores
+// words 4q .. 4q + 3 of the 16-word record
+//   [m01 m02 m11 m12 m22 | g01 g02 g03 g11 g12 g13 g21 g22 g23 | 0 0].
 // ---------------------------------------------------------------------------------------------
 constexpr int kRecBlock = 256;
+constexpr int kRecLanes = 4;
+constexpr int kRecBands = kFMax / kRecLanes;  // bands per lane at most
 
 template <typename TA, bool GRAD>
 __global__ __launch_bounds__(kRecBlock) void k_seg_rec(const EvalArgs a, int item0) {
@@ -942,7 +921,9 @@ __global__ __launch_bounds__(kRecBlock) void k_seg_rec(const EvalArgs a, int ite
     if (a.active && !as_const(a.active)[item]) return;
     const cptr<ItemDev> it = as_const(a.items) + item;
     const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
-    const int sg = (int)blockIdx.x * kRecBlock + (int)threadIdx.x;
+    const int q = (int)threadIdx.x % kRecLanes;
+    // whole quads leave together (the quad sums need every lane of a quad)
+    const int sg = ((int)blockIdx.x * kRecBlock + (int)threadIdx.x) / kRecLanes;
     if (sg >= L->nseg) return;
     const int F = a.nfreq;
     const cptr<BandDev> B = as_const(a.band);
@@ -953,36 +934,61 @@ __global__ __launch_bounds__(kRecBlock) void k_seg_rec(const EvalArgs a, int ite
     const gptr<TA> pd = tab + (int64_t)ld * F;
     const gptr<TA> bt = tab + (kd + 2 * (int64_t)lt) * F;
     const gptr<TA> ss = tab + (kd + 2 * kt + ls) * F;
+    TA pdv[kRecBands], btv[kRecBands], dtv[kRecBands], ssv[kRecBands];
+#pragma unroll
+    for (int i = 0; i < kRecBands; ++i) {
+        const int f0 = q + kRecLanes * i;
+        const int f = f0 < F ? f0 : F - 1;
+        pdv[i] = pd[f];
+        btv[i] = bt[2 * f];
+        dtv[i] = bt[2 * f + 1];
+        ssv[i] = ss[f];
+    }
     WAcc<TA> A = WAcc<TA>{};
-#pragma unroll 2
-    for (int f = 0; f < F; ++f) {
-        const TA ad = pd[f] * bt[2 * f], dt = bt[2 * f + 1], as = ss[f];
-        const TA w = Band<TA>::w(B, 0, f);
-        const TA wad = w * ad, was = w * as;
-        A.m01 += wad;
-        A.m02 += was;
-        A.m11 = fma(wad, ad, A.m11);
-        A.m12 = fma(wad, as, A.m12);
-        A.m22 = fma(was, as, A.m22);
-        if (GRAD) {
-            const TA c1 = wad * Band<TA>::ld(B, f), c2 = wad * dt, c3 = was * Band<TA>::ls(B, f);
-            A.g01 += c1;
-            A.g02 += c2;
-            A.g03 += c3;
-            A.g11 = fma(c1, ad, A.g11);
-            A.g12 = fma(c2, ad, A.g12);
-            A.g13 = fma(c3, ad, A.g13);
-            A.g21 = fma(c1, as, A.g21);
-            A.g22 = fma(c2, as, A.g22);
-            A.g23 = fma(c3, as, A.g23);
+#pragma unroll
+    for (int i = 0; i < kRecBands; ++i) {
+        const int f = q + kRecLanes * i;
+        if (f < F) {
+            const TA ad = pdv[i] * btv[i], dt = dtv[i], as = ssv[i];
+            const TA w = Band<TA>::w(B, 0, f);
+            const TA wad = w * ad, was = w * as;
+            A.m01 += wad;
+            A.m02 += was;
+            A.m11 = fma(wad, ad, A.m11);
+            A.m12 = fma(wad, as, A.m12);
+            A.m22 = fma(was, as, A.m22);
+            if (GRAD) {
+                const TA c1 = wad * Band<TA>::ld(B, f), c2 = wad * dt, c3 = was * Band<TA>::ls(B, f);
+                A.g01 += c1;
+                A.g02 += c2;
+                A.g03 += c3;
+                A.g11 = fma(c1, ad, A.g11);
+                A.g12 = fma(c2, ad, A.g12);
+                A.g13 = fma(c3, ad, A.g13);
+                A.g21 = fma(c1, as, A.g21);
+                A.g22 = fma(c2, as, A.g22);
+                A.g23 = fma(c3, as, A.g23);
+            }
         }
     }
     const TA z = (TA)0;
-    const TA rec[kRecWords] = {A.m01, A.m02, A.m11, A.m12, A.m22, A.g01, A.g02, A.g03,
-                               A.g11, A.g12, A.g13, A.g21, A.g22, A.g23, z,     z};
-    Col4<TA> *o = (Col4<TA> *)((TA *)a.segrec + (it->part_off + sg) * (int64_t)kRecWords);
+    TA rec[kRecWords] = {A.m01, A.m02, A.m11, A.m12, A.m22, A.g01, A.g02, A.g03,
+                         A.g11, A.g12, A.g13, A.g21, A.g22, A.g23, z,     z};
 #pragma unroll
-    for (int q = 0; q < kRecWords / 4; ++q) o[q] = Col4<TA>{rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]};
+    for (int w = 0; w < 14; ++w)
+        if (GRAD || w < 5) rec[w] = quad_sum(rec[w]);
+    Col4<TA> *o = (Col4<TA> *)((TA *)a.segrec + (it->part_off + sg) * (int64_t)kRecWords);
+    // lane q stores words 4q .. 4q + 3 (the quad's sums are in every lane)
+    TA v0 = rec[0], v1 = rec[1], v2 = rec[2], v3 = rec[3];
+#pragma unroll
+    for (int j = 1; j < kRecLanes; ++j)
+        if (q == j) {
+            v0 = rec[4 * j];
+            v1 = rec[4 * j + 1];
+            v2 = rec[4 * j + 2];
+            v3 = rec[4 * j + 3];
+        }
+    o[q] = Col4<TA>{v0, v1, v2, v3};
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1179,7 +1185,7 @@ static void launch_pixel_g(bool grad, int wm, int sm, size_t lds, dim3 grid, dim
 // segment records of every item (schedule mode 2), in the accumulation type of the mode
 static cs_status launch_seg_rec(const cs_problem *p, const EvalArgs &a, bool grad, bool fp32, hipStream_t s) {
     if (p->nseg_max < 1) return CS_OK;
-    const unsigned gx = (unsigned)((p->nseg_max + kRecBlock - 1) / kRecBlock);
+    const unsigned gx = (unsigned)(((int64_t)p->nseg_max * kRecLanes + kRecBlock - 1) / kRecBlock);
     for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
         const dim3 grid(gx, (unsigned)std::min(kMaxGridY, p->B - b0));
         if (fp32 && grad)

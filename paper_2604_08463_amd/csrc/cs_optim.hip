@@ -25,7 +25,9 @@ enum : int32_t { ST_INIT = 0, ST_REINIT = 1, ST_SEARCH = 2, ST_DONE = 3 };
 struct OptItem {
     double f, pg0, alpha, dec;
     int64_t nevals;
-    int32_t state, status, iter, nbt, npairs, newest, iter0, pad1;  // iter0: iterations before this phase
+    int32_t state, status, iter, nbt, npairs, newest;
+    int32_t iter0;  // iterations before this phase
+    int32_t sd;     // the direction is -Pg
     // AdaTopK: objective scale, bias-correction powers, last accepted step, step limit
     double scale, b1t, b2t, aprev, amax;
     int32_t t, lim, hit, pad2;
@@ -339,21 +341,41 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
         }
         pm = block_max<NT>(pm, red[0]);
         s.alpha = used ? 1.0 : (pm > 1.0 ? 1.0 / pm : 1.0);
+        s.sd = used ? 0 : 1;
         s.nbt = 0;
     }
 
     if (!finish && s.state != ST_DONE) {
-        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y)
-        double v[1] = {0.0};
-        for (int64_t i = tid; i < K; i += NT) {
-            double t = y[i] + s.alpha * p[i];
-            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-            yt[i] = t;
-            xt[i] = lo[i] + t * (hi[i] - lo[i]);
-            v[0] += g[i] * (t - y[i]);
+        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y).  The
+        // clamp can turn a descent direction into an ascending step (a coordinate next to a bound
+        // that p drives out of the box carries the descent); such a trial is not evaluated: unless
+        // p is already -Pg, the memory is cleared and the search restarts along -Pg, whose clamped
+        // steps always descend
+        for (;;) {
+            double v[1] = {0.0};
+            for (int64_t i = tid; i < K; i += NT) {
+                double t = y[i] + s.alpha * p[i];
+                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                yt[i] = t;
+                xt[i] = lo[i] + t * (hi[i] - lo[i]);
+                v[0] += g[i] * (t - y[i]);
+            }
+            block_sum<1, NT>(v, red);
+            s.dec = v[0];
+            if (s.dec < 0.0 || s.sd) break;
+            s.npairs = 0;
+            s.newest = -1;
+            s.sd = 1;
+            s.nbt = 0;
+            double pm = 0.0;
+            for (int64_t i = tid; i < K; i += NT) {
+                const double pi = is_free(y[i], g[i]) ? -g[i] : 0.0;
+                p[i] = pi;
+                pm = fmax(pm, fabs(pi));
+            }
+            pm = block_max<NT>(pm, red[0]);
+            s.alpha = pm > 1.0 ? 1.0 / pm : 1.0;
         }
-        block_sum<1, NT>(v, red);
-        s.dec = v[0];
         s.state = ST_SEARCH;
     }
     if (finish) {
@@ -630,25 +652,43 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
         }
         pm = block_max<NT>(pm, red[0]);
         s.alpha = used ? 1.0 : (pm > 1.0 ? 1.0 / pm : 1.0);
+        s.sd = used ? 0 : 1;
         s.nbt = 0;
     }
 
     if (!finish && s.state != ST_DONE) {
-        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y)
-        double v[1] = {0.0};
+        // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y); a
+        // clamped step that does not descend restarts the search along -Pg (as in k_opt_update)
+        for (;;) {
+            double v[1] = {0.0};
 #pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            const int64_t i = (int64_t)k * NT + tid;
-            if (i < K) {
-                double t = y[k] + s.alpha * pv[k];
-                t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-                ytg[i] = t;
-                xtg[i] = lo[i] + t * (hi[i] - lo[i]);
-                v[0] += g[k] * (t - y[k]);
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                if (i < K) {
+                    double t = y[k] + s.alpha * pv[k];
+                    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+                    ytg[i] = t;
+                    xtg[i] = lo[i] + t * (hi[i] - lo[i]);
+                    v[0] += g[k] * (t - y[k]);
+                }
             }
+            block_sum<1, NT>(v, red);
+            s.dec = v[0];
+            if (s.dec < 0.0 || s.sd) break;
+            s.npairs = 0;
+            s.newest = -1;
+            s.sd = 1;
+            s.nbt = 0;
+            double pm = 0.0;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                const int64_t i = (int64_t)k * NT + tid;
+                pv[k] = (i < K && is_free(y[k], g[k])) ? -g[k] : 0.0;
+                pm = fmax(pm, fabs(pv[k]));
+            }
+            pm = block_max<NT>(pm, red[0]);
+            s.alpha = pm > 1.0 ? 1.0 / pm : 1.0;
         }
-        block_sum<1, NT>(v, red);
-        s.dec = v[0];
         s.state = ST_SEARCH;
     }
 #pragma unroll

@@ -19,4 +19,5 @@ from .sky import (  # noqa: F401
     sky_sed_dust,
     sky_sed_sync,
     spherical_kmeans,
+    start_and_box,
 )

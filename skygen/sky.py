@@ -260,6 +260,12 @@ def _x0(nc) -> np.ndarray:
     return np.concatenate([np.full(int(nc[j]), X0[j]) for j in range(3)])
 
 
+def start_and_box(nc) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Optimiser start ``x0`` (X0 for every cluster) and box bounds for cluster counts ``nc``."""
+    lo, hi = _box(nc)
+    return _x0(nc), lo, hi
+
+
 def _clip_truth(t: np.ndarray) -> np.ndarray:
     out = t.copy()
     for j in range(3):

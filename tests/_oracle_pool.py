@@ -21,13 +21,10 @@ def workers() -> int:
 
 
 def box_start(keff):
-    """Start point and box of the optimiser for cluster counts keff (the generator's X0, BOUNDS)."""
+    """Start point and box of the optimiser for cluster counts keff (the generator's)."""
     import skygen
 
-    x0 = np.concatenate([np.full(int(keff[j]), skygen.X0[j]) for j in range(3)])
-    lo = np.concatenate([np.full(int(keff[j]), skygen.BOUNDS[j][0]) for j in range(3)])
-    hi = np.concatenate([np.full(int(keff[j]), skygen.BOUNDS[j][1]) for j in range(3)])
-    return x0, lo, hi
+    return skygen.start_and_box(keff)
 
 
 def _lbfgs(args):

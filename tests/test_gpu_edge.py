@@ -1,6 +1,7 @@
 """Edge cases of the HIP path against the oracle: an item whose pixels are all excluded, a
-single-pixel sky, fewer bands than components (every pixel degenerate), and one cluster per pixel
-(every chunk takes the direct-gather path)."""
+single-pixel sky, fewer bands than components (every pixel degenerate), one cluster per pixel
+(every chunk takes the direct-gather path), and non-finite data or weights (data faults set status
+bits, never crash)."""
 
 import numpy as np
 import pytest
@@ -79,3 +80,38 @@ def test_one_cluster_per_pixel():
         for sh in (0, 1, 2):
             prob.set_schedule(4, 0, 1, sh)
             compare(sky, prob, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_non_finite_data_and_weights_set_status_like_the_oracle(precision):
+    # data faults never crash: a NaN or an infinity in d, or a NaN per-pixel weight, makes F NaN
+    # and sets the same status bits as the oracle; the other items of the batch are untouched
+    sky = skygen.make_tiny(300, 15, (4, 3, 2), seed=61, nitems=3)
+    d = sky.d.clone()
+    d[1, 0, 5, 17] = float("nan")
+    d[2, 1, 3, 40] = float("inf")
+    sky.d = d
+    prob = cs.Problem.from_sky(sky, precision)
+    f, _, _, st = gpu_eval(prob, sky, cluster=False)
+    for b in range(3):
+        fo, _, _, so = oracle.Problem.from_sky(sky, b).likelihood_grad(sky.x[b])
+        _log(f"{precision} band weights item {b}: status {st[b]} / oracle {so}, F {f[b]} / {fo}")
+        assert st[b] == so and np.isfinite(f[b]) == np.isfinite(fo)
+    assert st[0] == 0 and np.isfinite(f[0]) and st[1] & cs.NONFINITE and st[2] & cs.NONFINITE
+    # per-pixel weights with a NaN in item 0
+    sky.d = sky.d.clone()
+    sky.d[1, 0, 5, 17] = 1.0
+    sky.d[2, 1, 3, 40] = 1.0
+    wpix = np.repeat(sky.ninv[:, :, None], sky.npix, axis=2)
+    wpix = np.stack([wpix] * 3)
+    wpix[0, 1, 7, 99] = np.nan
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    prob2 = cs.Problem(sky.freqs, sky.d.to("cuda", dt), torch.as_tensor(wpix, dtype=dt).cuda(), sky.labels.cuda(),
+                       sky.nclusters, nitems=3, precision=precision)
+    f2, _, _, st2 = gpu_eval(prob2, sky, cluster=False)
+    for b in range(3):
+        pr = oracle.Problem(sky.freqs, sky.item_d(b), wpix[b], sky.item_labels(b), sky.nclusters[b])
+        fo, _, _, so = pr.likelihood_grad(sky.x[b])
+        _log(f"{precision} pixel weights item {b}: status {st2[b]} / oracle {so}, F {f2[b]} / {fo}")
+        assert st2[b] == so and np.isfinite(f2[b]) == np.isfinite(fo)
+    assert np.isnan(f2[0]) and st2[0] & cs.NOT_PD and st2[1] == 0 and st2[2] == 0

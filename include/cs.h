@@ -50,9 +50,8 @@ typedef enum {
  *   CS_FP64       : FP64 storage, FP64 frequency accumulation, FP64 solve and reductions.
  *   CS_FP32_BULK  : FP32 storage and FP32 frequency accumulation of every per-band sum
  *                   (A^T N^-1 A, A^T N^-1 d and the adjoint sums), whichever schedule forms them
- *                   (per pixel, per segment inside the pixel kernel, or per segment in a
- *                   pre-pass); FP64 3x3 Cholesky solve from those sums; FP64 compensated
- *                   per-cluster reductions.
+ *                   (per pixel, or once per segment inside the pixel kernel); FP64 3x3 Cholesky
+ *                   solve from those sums; FP64 compensated per-cluster reductions.
  *   CS_FP32_STORE : FP32 storage, FP64 accumulation, solve and reductions.  */
 typedef enum { CS_FP64 = 0, CS_FP32_BULK = 1, CS_FP32_STORE = 2 } cs_precision;
 

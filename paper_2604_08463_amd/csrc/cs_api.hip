@@ -75,9 +75,6 @@ static void carve(cs_problem *p) {
     w.wpack = take(p->nmode == CS_NINV_PIXEL ? elem * 2 * (size_t)p->F * kChunk * w.nchunk_max * B : 0);
     w.tables = take(sizeof(double) * (size_t)p->F * (size_t)p->taboff[p->B]);
     w.partials = take(sizeof(double) * 4 * w.p64 * B);
-    // segment records in FP64 words: the mixed-precision optimiser evaluates an FP32-bulk problem
-    // with FP64 accumulation too
-    w.segrec = take(sizeof(double) * kRecWords * w.p64 * B);
     w.segoff = take(sizeof(int64_t) * (B + 1));
     w.istatus = take(sizeof(int32_t) * B);
     w.fpart = take(sizeof(double) * 2 * kFSlices * B);
@@ -248,7 +245,6 @@ cs_status cs_problem_prepare(cs_problem *p, void *workspace, size_t bytes, void 
     hipStream_t s = (hipStream_t)stream;
     p->wsp = (char *)workspace;
     p->prepared = false;
-    p->nseg_max = 0;
     const WsLayout &w = p->ws;
     char *base = p->wsp;
 
@@ -304,7 +300,6 @@ cs_status cs_problem_prepare(cs_problem *p, void *workspace, size_t bytes, void 
         L.n_incl = counts[4 * l];
         L.nseg = counts[4 * l + 1];
         L.nchunks = (L.n_incl + kChunk - 1) / kChunk;
-        p->nseg_max = std::max(p->nseg_max, L.nseg);
     }
     for (int b = 0; b < p->B; ++b) {
         const LayoutDev &L = p->layouts[p->items[b].layout];
@@ -514,7 +509,7 @@ cs_status cs_problem_set_schedule(cs_problem *p, const cs_schedule *s) {
     if (!p || !s) return invalid("null argument");
     const int w = s->waves_per_block;
     if (!(w == 1 || w == 2 || w == 4 || w == 8) || s->blocks_per_cu < 0 || s->blocks_per_cu > 64 ||
-        (s->xcd_remap != 0 && s->xcd_remap != 1) || s->shared_segments < 0 || s->shared_segments > 2)
+        (s->xcd_remap != 0 && s->xcd_remap != 1) || (s->shared_segments != 0 && s->shared_segments != 1))
         return invalid("bad schedule");
     p->sched = *s;
     return CS_OK;
@@ -567,7 +562,7 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
         }
         return true;
     };
-    for (int sh = 0; sh < 3 && rc == CS_OK; ++sh)
+    for (int sh = 0; sh < 2 && rc == CS_OK; ++sh)
         for (int wi = 0; wi < 4 && rc == CS_OK; ++wi)
             for (int bi = 0; bi < 3 && rc == CS_OK; ++bi)
                 for (int xr = 0; xr < 2 && rc == CS_OK; ++xr) {

@@ -1,8 +1,6 @@
 // One batched evaluation of the spectral likelihood and its adjoint (paper Sec. 2.1, 3.3.1).
 //
 //   k_sed          per (item, cluster, band group): SED tables of the three spectral parameters (a2)
-//   k_seg_rec      per (item, segment): A^T N^-1 A and the adjoint sums G_jk of the segment's label
-//                  triple, once per segment (the schedule that shares them through records)
 //   k_pixel_stage  per 64-pixel chunk (one wavefront): the chunk's SED columns staged in LDS, the
 //                  mixing matrix per pixel (a3), frequency accumulation of A^T N^-1 A, A^T N^-1 d
 //                  and the adjoint sums (a4), FP64 3x3 Cholesky (a5), per-pixel gradient (a6),
@@ -410,15 +408,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
 // the streaming data loads (a ring of kRing groups prefetched ahead) and reads the coefficients
 // from LDS, whose counter is separate from the vector-memory counter: no table gather ever
 // waits behind a data load.  M = A^T N^-1 A and the adjoint sums G_jk depend only on a pixel's
-// labels; three ways to form them (SM):
-//   0 per pixel: every lane accumulates them over the bands itself;
-//   1 segment-shared: while staging, four lanes per segment accumulate them over interleaved
-//     bands and add their partials, and one of them forms the FP64 Cholesky factor of M into the
-//     slice; every pixel then accumulates only its data-dependent sums b and h (12 FMAs per band)
-//     and reads its segment's factor;
-//   2 segment records: k_seg_rec has summed them once per segment; each pixel accumulates only
-//     b and h (the five band products and 12 FMAs per band, against 31 operations in mode 0),
-//     then reads its segment's record and forms its FP64 Cholesky factor from it.
+// labels; two ways to form them:
+//   per-pixel (SHARED = false): every lane accumulates them over the bands itself;
+//   segment-shared (SHARED = true): while staging, four lanes per segment accumulate them over
+//     interleaved bands and add their partials, and one of them forms the FP64 Cholesky factor
+//     of M into the slice; every pixel then accumulates only its data-dependent sums b and h
+//     (12 FMAs per band) and reads its segment's factor.
 // Chunks with more than kStageSeg segments take the direct-gather per-pixel path.
 // ---------------------------------------------------------------------------------------------
 // Per segment: the Cholesky factor of M (inverse diagonal), G_jk and a positive-definite flag,
@@ -446,11 +441,10 @@ template <typename TA>
 __host__ __device__ constexpr size_t stage_c5_bytes(int F) {
     return ((size_t)kStageSeg * (size_t)F * sizeof(TA) + 15) & ~(size_t)15;
 }
-template <typename TA, int SM>
+template <typename TA, bool SHARED>
 __host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
-    return SM == 1   ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
-           : SM == 2 ? stage_col_bytes<TA>(F)
-                     : stage_col_bytes<TA>(F);
+    return SHARED ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
+                  : stage_col_bytes<TA>(F);
 }
 
 // Sum over the four lanes of a quad, the same value in each: (v0 + v1) + (v2 + v3) via DPP
@@ -473,12 +467,9 @@ __device__ __forceinline__ T quad_sum(T v) {
     return v;
 }
 
-template <typename TS, typename TA, bool GRAD, int SM>
+template <typename TS, typename TA, bool GRAD, bool SHARED>
 __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, const int chunk, const int lane,
                                             char *wave_lds) {
-    constexpr bool SHARED = SM == 1;  // per-segment sums formed while staging
-    constexpr bool RECS = SM == 2;    // per-segment sums read from the segment records
-    constexpr bool PREMUL = SHARED;   // staged coefficients premultiplied by the band constants
     // groups of kG bands in flight per lane: the segment-shared band loop is short (12 FMAs per
     // band), so it looks further ahead (measured on gfx950: 8 groups for it; 6 for per-pixel with
     // FP32 accumulation, 4 with FP64, whose registers would otherwise cost it a wavefront)
@@ -724,7 +715,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     auto band = [&](const int f, const TA d0, const TA d1) {
         const Col4<TA> c = mycols[f];
         const TA w = Band<TA>::w(B, 0, f);
-        if (PREMUL) {
+        if (SHARED) {
             const TA c3 = myc5[f];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -745,14 +736,12 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const TA lgd = Band<TA>::ld(B, f), lgs = Band<TA>::ls(B, f);
         const TA wad = w * ad, was = w * as;
         const TA c1 = wad * lgd, c2 = wad * dt, c3 = was * lgs;
-        if (!RECS) {  // the record mode reads M and G from its segment's record
-            A.m01 += wad;
-            A.m02 += was;
-            A.m11 = fma(wad, ad, A.m11);
-            A.m12 = fma(wad, as, A.m12);
-            A.m22 = fma(was, as, A.m22);
-        }
-        if (GRAD && !RECS) {
+        A.m01 += wad;
+        A.m02 += was;
+        A.m11 = fma(wad, ad, A.m11);
+        A.m12 = fma(wad, as, A.m12);
+        A.m22 = fma(was, as, A.m22);
+        if (GRAD) {
             A.g01 += c1;
             A.g02 += c2;
             A.g03 += c3;
@@ -814,12 +803,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         ok = R[kOk * kStageSeg] != 0.0;
     } else {
         const double m00 = (double)Band<TA>::wsum(B, 0);
-        // record of the pixel's segment (mode 2), read after the band loop: the lanes of one
-        // segment read the same 64 bytes
-        const gptr<TA> R = as_global((const TA *)a.segrec) + (it->part_off + segbase + segl) * (int64_t)kRecWords;
-        const double m01 = RECS ? (double)R[0] : (double)A.m01, m02 = RECS ? (double)R[1] : (double)A.m02,
-                     m11 = RECS ? (double)R[2] : (double)A.m11, m12 = RECS ? (double)R[3] : (double)A.m12,
-                     m22 = RECS ? (double)R[4] : (double)A.m22;
+        const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;
         i00 = 1.0 / sqrt(m00);
         l10 = m01 * i00;
         l20 = m02 * i00;
@@ -829,14 +813,9 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const double p2 = m22 - l20 * l20 - l21 * l21;
         i22 = 1.0 / sqrt(p2);
         ok = pd_pivots<TA>(m00, m11, m22, p1, p2);
-        if (RECS) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) G[q] = GRAD ? (double)R[5 + q] : 0.0;
-        } else {
-            G[0] = A.g01; G[1] = A.g02; G[2] = A.g03;
-            G[3] = A.g11; G[4] = A.g12; G[5] = A.g13;
-            G[6] = A.g21; G[7] = A.g22; G[8] = A.g23;
-        }
+        G[0] = A.g01; G[1] = A.g02; G[2] = A.g03;
+        G[3] = A.g11; G[4] = A.g12; G[5] = A.g13;
+        G[6] = A.g21; G[7] = A.g22; G[8] = A.g23;
     }
     double fpix = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
 #pragma unroll
@@ -872,15 +851,15 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     __builtin_amdgcn_wave_barrier();
 }
 
-// Minimum wavefronts per SIMD the register allocation must allow: five in the per-pixel and record
-// modes with FP32 accumulation (at most 96 VGPRs); the other modes are left to the compiler.
-template <typename TA, int SM>
+// Minimum wavefronts per SIMD the register allocation must allow: five in the per-pixel mode with
+// FP32 accumulation (at most 96 VGPRs); the other modes are left to the compiler.
+template <typename TA, bool SHARED>
 constexpr int stage_waves() {
-    return SM == 1 ? 1 : (sizeof(TA) == 4 ? 5 : 1);
+    return SHARED ? 1 : (sizeof(TA) == 4 ? 5 : 1);
 }
 
-template <typename TS, typename TA, bool GRAD, int SM>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<TA, SM>()))) void k_pixel_stage(
+template <typename TS, typename TA, bool GRAD, bool SHARED>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<TA, SHARED>()))) void k_pixel_stage(
     const EvalArgs a) {
     extern __shared__ char smem[];
     const int lane = threadIdx.x & 63;
@@ -889,7 +868,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
     const int64_t nb = gridDim.x;
     const int64_t lb = logical_block(a.xcd_remap);
     const cptr<int> units = as_const((const int *)a.units);
-    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA, SM>(a.nfreq);
+    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA, SHARED>(a.nfreq);
     for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
         const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
         const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
@@ -897,98 +876,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
         const cptr<LayoutDev> L = as_const(a.layouts) + (as_const(a.items) + item)->layout;
         const int nseg = as_const(L->seg_base)[chunk + 1] - as_const(L->seg_base)[chunk];
         if (nseg <= kStageSeg)
-            unit_staged<TS, TA, GRAD, SM>(a, item, chunk, lane, wave_lds);
+            unit_staged<TS, TA, GRAD, SHARED>(a, item, chunk, lane, wave_lds);
         else
             unit_pixel<TS, TA, GRAD, 0, 0>(a, item, chunk, lane);
     }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Segment records (schedule mode 2): M = A^T N^-1 A (upper triangle without m00, which is the band
-// weight sum) and, for the gradient, G_jk of each segment's label triple.  Four lanes per (item,
-// segment): lane q of the quad sums the bands q, q + 4, ... (all its table gathers issued first),
-// then DPP quad sums combine the four partial sums (the same value in each lane) and lane q stores
-// words 4q .. 4q + 3 of the 16-word record
-//   [m01 m02 m11 m12 m22 | g01 g02 g03 g11 g12 g13 g21 g22 g23 | 0 0].
-// ---------------------------------------------------------------------------------------------
-constexpr int kRecBlock = 256;
-constexpr int kRecLanes = 4;
-constexpr int kRecBands = kFMax / kRecLanes;  // bands per lane at most
-
-template <typename TA, bool GRAD>
-__global__ __launch_bounds__(kRecBlock) void k_seg_rec(const EvalArgs a, int item0) {
-    const int item = item0 + (int)blockIdx.y;
-    if (a.active && !as_const(a.active)[item]) return;
-    const cptr<ItemDev> it = as_const(a.items) + item;
-    const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
-    const int q = (int)threadIdx.x % kRecLanes;
-    // whole quads leave together (the quad sums need every lane of a quad)
-    const int sg = ((int)blockIdx.x * kRecBlock + (int)threadIdx.x) / kRecLanes;
-    if (sg >= L->nseg) return;
-    const int F = a.nfreq;
-    const cptr<BandDev> B = as_const(a.band);
-    const gptr<int> lab = as_global((const int *)L->seg_lab) + 4 * (int64_t)sg;
-    const int ld = lab[0], lt = lab[1], ls = lab[2];
-    const int64_t kd = it->k[0], kt = it->k[1];
-    const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
-    const gptr<TA> pd = tab + (int64_t)ld * F;
-    const gptr<TA> bt = tab + (kd + 2 * (int64_t)lt) * F;
-    const gptr<TA> ss = tab + (kd + 2 * kt + ls) * F;
-    TA pdv[kRecBands], btv[kRecBands], dtv[kRecBands], ssv[kRecBands];
-#pragma unroll
-    for (int i = 0; i < kRecBands; ++i) {
-        const int f0 = q + kRecLanes * i;
-        const int f = f0 < F ? f0 : F - 1;
-        pdv[i] = pd[f];
-        btv[i] = bt[2 * f];
-        dtv[i] = bt[2 * f + 1];
-        ssv[i] = ss[f];
-    }
-    WAcc<TA> A = WAcc<TA>{};
-#pragma unroll
-    for (int i = 0; i < kRecBands; ++i) {
-        const int f = q + kRecLanes * i;
-        if (f < F) {
-            const TA ad = pdv[i] * btv[i], dt = dtv[i], as = ssv[i];
-            const TA w = Band<TA>::w(B, 0, f);
-            const TA wad = w * ad, was = w * as;
-            A.m01 += wad;
-            A.m02 += was;
-            A.m11 = fma(wad, ad, A.m11);
-            A.m12 = fma(wad, as, A.m12);
-            A.m22 = fma(was, as, A.m22);
-            if (GRAD) {
-                const TA c1 = wad * Band<TA>::ld(B, f), c2 = wad * dt, c3 = was * Band<TA>::ls(B, f);
-                A.g01 += c1;
-                A.g02 += c2;
-                A.g03 += c3;
-                A.g11 = fma(c1, ad, A.g11);
-                A.g12 = fma(c2, ad, A.g12);
-                A.g13 = fma(c3, ad, A.g13);
-                A.g21 = fma(c1, as, A.g21);
-                A.g22 = fma(c2, as, A.g22);
-                A.g23 = fma(c3, as, A.g23);
-            }
-        }
-    }
-    const TA z = (TA)0;
-    TA rec[kRecWords] = {A.m01, A.m02, A.m11, A.m12, A.m22, A.g01, A.g02, A.g03,
-                         A.g11, A.g12, A.g13, A.g21, A.g22, A.g23, z,     z};
-#pragma unroll
-    for (int w = 0; w < 14; ++w)
-        if (GRAD || w < 5) rec[w] = quad_sum(rec[w]);
-    Col4<TA> *o = (Col4<TA> *)((TA *)a.segrec + (it->part_off + sg) * (int64_t)kRecWords);
-    // lane q stores words 4q .. 4q + 3 (the quad's sums are in every lane)
-    TA v0 = rec[0], v1 = rec[1], v2 = rec[2], v3 = rec[3];
-#pragma unroll
-    for (int j = 1; j < kRecLanes; ++j)
-        if (q == j) {
-            v0 = rec[4 * j];
-            v1 = rec[4 * j + 1];
-            v2 = rec[4 * j + 2];
-            v3 = rec[4 * j + 3];
-        }
-    o[q] = Col4<TA>{v0, v1, v2, v3};
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1160,13 +1051,11 @@ __global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2log
 // wm == 0 (band weights shared by Q and U): the LDS-staged kernel, lds bytes per workgroup;
 // otherwise the direct-gather kernel with separate Q/U (wm = 1) or per-pixel (wm = 2) weights.
 template <typename TS, typename TA, bool GRAD>
-static void launch_pixel_t(int wm, int sm, size_t lds, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    if (wm == 0 && sm == 1)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 1>), grid, block, lds, s, a);
-    else if (wm == 0 && sm == 2)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 2>), grid, block, lds, s, a);
+static void launch_pixel_t(int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
+    if (wm == 0 && shared)
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, true>), grid, block, lds, s, a);
     else if (wm == 0)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 0>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, false>), grid, block, lds, s, a);
     else if (wm == 1)
         hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, 0>), grid, block, 0, s, a);
     else
@@ -1174,40 +1063,18 @@ static void launch_pixel_t(int wm, int sm, size_t lds, dim3 grid, dim3 block, hi
 }
 
 template <typename TS, typename TA>
-static void launch_pixel_g(bool grad, int wm, int sm, size_t lds, dim3 grid, dim3 block, hipStream_t s,
+static void launch_pixel_g(bool grad, int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s,
                            const EvalArgs &a) {
     if (grad)
-        launch_pixel_t<TS, TA, true>(wm, sm, lds, grid, block, s, a);
+        launch_pixel_t<TS, TA, true>(wm, shared, lds, grid, block, s, a);
     else
-        launch_pixel_t<TS, TA, false>(wm, sm, lds, grid, block, s, a);
-}
-
-// segment records of every item (schedule mode 2), in the accumulation type of the mode
-static cs_status launch_seg_rec(const cs_problem *p, const EvalArgs &a, bool grad, bool fp32, hipStream_t s) {
-    if (p->nseg_max < 1) return CS_OK;
-    const unsigned gx = (unsigned)(((int64_t)p->nseg_max * kRecLanes + kRecBlock - 1) / kRecBlock);
-    for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
-        const dim3 grid(gx, (unsigned)std::min(kMaxGridY, p->B - b0));
-        if (fp32 && grad)
-            hipLaunchKernelGGL((k_seg_rec<float, true>), grid, dim3(kRecBlock), 0, s, a, b0);
-        else if (fp32)
-            hipLaunchKernelGGL((k_seg_rec<float, false>), grid, dim3(kRecBlock), 0, s, a, b0);
-        else if (grad)
-            hipLaunchKernelGGL((k_seg_rec<double, true>), grid, dim3(kRecBlock), 0, s, a, b0);
-        else
-            hipLaunchKernelGGL((k_seg_rec<double, false>), grid, dim3(kRecBlock), 0, s, a, b0);
-        CSI_HIP(hipGetLastError());
-    }
-    return CS_OK;
+        launch_pixel_t<TS, TA, false>(wm, shared, lds, grid, block, s, a);
 }
 
 // LDS slice of one wavefront of the staged kernel in an arithmetic mode
-static size_t stage_bytes(cs_precision mode, int sm, int F) {
-    if (mode == CS_FP32_BULK)
-        return sm == 1 ? stage_bytes_per_wave<float, 1>(F)
-                       : (sm == 2 ? stage_bytes_per_wave<float, 2>(F) : stage_bytes_per_wave<float, 0>(F));
-    return sm == 1 ? stage_bytes_per_wave<double, 1>(F)
-                   : (sm == 2 ? stage_bytes_per_wave<double, 2>(F) : stage_bytes_per_wave<double, 0>(F));
+static size_t stage_bytes(cs_precision mode, bool shared, int F) {
+    if (mode == CS_FP32_BULK) return shared ? stage_bytes_per_wave<float, true>(F) : stage_bytes_per_wave<float, false>(F);
+    return shared ? stage_bytes_per_wave<double, true>(F) : stage_bytes_per_wave<double, false>(F);
 }
 
 EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active) {
@@ -1222,7 +1089,6 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
     a.tables = p->wsp + w.tables;
     a.band = (const BandDev *)(p->wsp + w.band);
     a.partials = (double *)(p->wsp + w.partials);
-    a.segrec = p->wsp + w.segrec;
     a.istatus = (int32_t *)(p->wsp + w.istatus);
     a.fpart = (double *)(p->wsp + w.fpart);
     a.active = active;
@@ -1262,15 +1128,11 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     if (sst != CS_OK) return sst;
 
     const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
-    const int sm = wm == 0 ? p->sched.shared_segments : 0;
-    if (sm == 2) {
-        const cs_status rst = launch_seg_rec(p, a, want_grad, mode == CS_FP32_BULK, s);
-        if (rst != CS_OK) return rst;
-    }
+    const bool shared = p->sched.shared_segments != 0;
     // the staged kernel's workgroup holds at most 64 KiB of LDS: fewer wavefronts per workgroup
     // when the slices do not fit (same arithmetic, work only regrouped)
     int wpb = p->sched.waves_per_block;
-    const size_t per_wave = wm == 0 ? stage_bytes(mode, sm, p->F) : 0;
+    const size_t per_wave = wm == 0 ? stage_bytes(mode, shared, p->F) : 0;
     while (wpb > 1 && per_wave * (size_t)wpb > 65536) wpb >>= 1;
     a.waves_per_block = wpb;
     int64_t nblocks = (p->nunits + wpb - 1) / wpb;
@@ -1292,11 +1154,11 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
         CSI_HIP(hipEventRecord(e0, s));
     }
     if (mode == CS_FP64)
-        launch_pixel_g<double, double>(want_grad, wm, sm, lds, grid, block, s, a);
+        launch_pixel_g<double, double>(want_grad, wm, shared, lds, grid, block, s, a);
     else if (mode == CS_FP32_BULK)
-        launch_pixel_g<float, float>(want_grad, wm, sm, lds, grid, block, s, a);
+        launch_pixel_g<float, float>(want_grad, wm, shared, lds, grid, block, s, a);
     else
-        launch_pixel_g<float, double>(want_grad, wm, sm, lds, grid, block, s, a);
+        launch_pixel_g<float, double>(want_grad, wm, shared, lds, grid, block, s, a);
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 

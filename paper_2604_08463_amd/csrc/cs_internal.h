@@ -18,7 +18,6 @@ constexpr int kFSlices = 8;     // slices of an item's segments summed by separa
 constexpr int kSegLabPad = 16;  // records past the end of each seg_lab array (read, never used)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int kNumCu = 256;
-constexpr int kRecWords = 16;  // words of one segment record (A^T N^-1 A and G_jk, padded)
 constexpr int kMaxGridY = 65535;  // largest grid dimension y
 
 // Per-band constants, computed on the host in FP64 and stored once in the workspace.
@@ -76,7 +75,6 @@ struct EvalArgs {
     void *tables;        // per item: PD [K_d][F], BTDT [K_T][F][2], SS [K_s][F]
     const BandDev *band;
     double *partials;    // [segment][4]: f, dF/dbeta_d, dF/dT_d, dF/dbeta_s
-    void *segrec;        // [segment][kRecWords] in the accumulation type: M and G of each segment
     int32_t *istatus;    // [B] status bits of the current evaluation
     double *fpart;       // [B][kFSlices][2]: compensated partial sums of F per slice of segments
     const int32_t *active;  // nullable [B]: 0 = skip item (converged optimiser items)
@@ -90,7 +88,7 @@ struct EvalArgs {
 // Workspace regions (byte offsets, 256-aligned), see carve_workspace().
 struct WsLayout {
     size_t band, items, layouts, units, keys, order, head, seg_base, seg_lab, seg_perm, seg_off,
-        counts, dpack, wpack, tables, partials, segrec, segoff, istatus, fpart, total;
+        counts, dpack, wpack, tables, partials, segoff, istatus, fpart, total;
     size_t keys_stride, p64, nchunk_max, np2, kmax[3];
 };
 
@@ -128,7 +126,6 @@ struct cs_problem {
     std::vector<csi::ItemDev> items;
     std::vector<csi::LayoutDev> layouts;
     int64_t nunits = 0;
-    int32_t nseg_max = 0;  // most segments of one layout
     cs_schedule sched{4, 0, 1, 1};
     // kernel timing
     bool timing = false;

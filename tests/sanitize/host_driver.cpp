@@ -54,12 +54,12 @@ int main() {
     size_t ows = 0;
     CHECK(cs_optimizer_workspace_bytes(p, 10, &ows) == CS_OK && ows > 0);
     CHECK(cs_optimizer_workspace_bytes(p, 33, &ows) == CS_E_INVALID);
-    cs_schedule s{2, 0, 1, 2};
+    cs_schedule s{2, 0, 1, 1};
     CHECK(cs_problem_set_schedule(p, &s) == CS_OK);
-    s.shared_segments = 3;
+    s.shared_segments = 2;
     CHECK(cs_problem_set_schedule(p, &s) == CS_E_INVALID);
     cs_schedule g{};
-    CHECK(cs_problem_get_schedule(p, &g) == CS_OK && g.shared_segments == 2);
+    CHECK(cs_problem_get_schedule(p, &g) == CS_OK && g.shared_segments == 1 && g.waves_per_block == 2);
     double *fake = (double *)0x300000;
     CHECK(cs_likelihood(p, fake, fake, nullptr, nullptr) == CS_E_STATE);
     CHECK(cs_likelihood_grad(p, fake, fake, fake, nullptr, nullptr, nullptr) == CS_E_STATE);

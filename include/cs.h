@@ -195,6 +195,21 @@ cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const u
                           int64_t labels_stride, int32_t *keff, void *workspace, size_t bytes,
                           void *stream);
 
+/* Allocation-free K-means, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cs_kmeans_batch with its
+ * workspace taken from a device array owned by the library, CS_KMEANS_STATIC_BYTES (128 MiB) on
+ * every GPU it runs on, held from the module load until the process ends.  Returns CS_E_WORKSPACE
+ * when cs_kmeans_workspace_bytes of the arguments exceeds that size (split the tasks over several
+ * calls).  Every call on one GPU uses the same array, which keeps the last call's contents (each
+ * call initialises what it reads): calls that overlap on one GPU -- on other streams or host
+ * threads -- race, so the caller serialises them.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  Synchronises the stream once (upload of k), like cs_kmeans_batch. */
+#define CS_KMEANS_STATIC_BYTES ((size_t)128 << 20)
+cs_status cs_kmeans_batch_static(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep,
+                                 int64_t keep_stride, const int32_t *k, const int32_t *init,
+                                 int64_t init_stride, int32_t iters, int32_t *labels,
+                                 int64_t labels_stride, int32_t *keff, void *stream);
+
 /* Batched bound-constrained optimisers on the device, in the internal box y = (x - l)/(u - l)
  * (paper App. A.1) with bound clamping as in Alg. 1:
  *   CS_SOLVER_LBFGS    projected L-BFGS (two-loop recursion on the free set, Armijo backtracking)

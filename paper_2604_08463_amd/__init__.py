@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     default_opts,
     item_range,
     kmeans_batch,
+    kmeans_batch_static,
     load,
 )
 from .autograd import CsLikelihood, neg2logl  # noqa: F401

@@ -63,7 +63,7 @@ _lib = None
 EXPORTS = [
     "cs_problem_create", "cs_problem_param_offsets", "cs_problem_workspace_bytes", "cs_problem_prepare",
     "cs_problem_item_info", "cs_problem_segments", "cs_likelihood", "cs_likelihood_grad", "cs_component_maps",
-    "cs_kmeans_workspace_bytes", "cs_kmeans_batch", "cs_optim_default_opts",
+    "cs_kmeans_workspace_bytes", "cs_kmeans_batch", "cs_kmeans_batch_static", "cs_optim_default_opts",
     "cs_optimizer_workspace_bytes", "cs_optimize_batch", "cs_optimize_batch_run", "cs_item_range",
     "cs_problem_desc_slice", "cs_problem_get_schedule", "cs_problem_set_schedule",
     "cs_problem_autotune", "cs_problem_set_timing", "cs_problem_kernel_time", "cs_problem_destroy", "cs_status_str",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.cs_component_maps.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.cs_kmeans_workspace_bytes.argtypes = [i64, i32, P(i32), P(C.c_size_t)]
     L.cs_kmeans_batch.argtypes = [vp, i64, i32, vp, i64, P(i32), vp, i64, i32, vp, i64, vp, vp, C.c_size_t, vp]
+    L.cs_kmeans_batch_static.argtypes = [vp, i64, i32, vp, i64, P(i32), vp, i64, i32, vp, i64, vp, vp]
     L.cs_optim_default_opts.argtypes = [P(OptimOpts)]
     L.cs_optimizer_workspace_bytes.argtypes = [vp, i32, P(C.c_size_t)]
     L.cs_optimize_batch.argtypes = [vp, P(OptimOpts), vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
@@ -210,6 +211,30 @@ def kmeans_batch(vecs: torch.Tensor, k, init: torch.Tensor, keep: torch.Tensor |
                              _ptr(keff), wp, nb.value, _stream(stream)), "cs_kmeans_batch")
     if stream is not None:
         ws.record_stream(stream)  # the workspace is released in that stream's order
+    return labels, keff
+
+
+def kmeans_batch_static(vecs: torch.Tensor, k, init: torch.Tensor, keep: torch.Tensor | None = None,
+                        iters: int = 20, stream=None):
+    """As :func:`kmeans_batch`, on the library's own per-GPU scratch array (no workspace is
+    allocated); raises when the tasks need more than CS_KMEANS_STATIC_BYTES."""
+    L = load()
+    vecs = vecs.to(torch.float64).contiguous()
+    n = vecs.shape[0]
+    kk = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(-1))
+    T = kk.size
+    init = init.to(torch.int32).contiguous()
+    if init.dim() != 2 or init.shape[0] != T:
+        raise ValueError("init must be [T][>= max k]")
+    if keep is not None:
+        keep = keep.to(torch.uint8).contiguous()
+        if keep.shape != (T, n):
+            raise ValueError("keep must be [T][n]")
+    labels = torch.empty((T, n), dtype=torch.int32, device=vecs.device)
+    keff = torch.empty(T, dtype=torch.int32, device=vecs.device)
+    _check(L.cs_kmeans_batch_static(_ptr(vecs), n, T, _ptr(keep), 0, kk.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    _ptr(init), init.shape[1], iters, _ptr(labels), 0, _ptr(keff), _stream(stream)),
+           "cs_kmeans_batch_static")
     return labels, keff
 
 

@@ -416,6 +416,24 @@ cs_status cs_kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const u
                         workspace, (hipStream_t)stream);
 }
 
+cs_status cs_kmeans_batch_static(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep,
+                                 int64_t keep_stride, const int32_t *k, const int32_t *init, int64_t init_stride,
+                                 int32_t iters, int32_t *labels, int64_t labels_stride, int32_t *keff, void *stream) {
+    int64_t ktot = 0;
+    cs_status st = kmeans_check(n, ntasks, k, &ktot);
+    if (st != CS_OK) return st;
+    if (!vecs || !init || !labels || !keff) return invalid("null argument");
+    if (iters < 0) return invalid("iters must be >= 0");
+    int32_t kmax = 1;
+    for (int32_t i = 0; i < ntasks; ++i) kmax = std::max(kmax, k[i]);
+    if (keep_stride == 0) keep_stride = n;
+    if (labels_stride == 0) labels_stride = n;
+    if (init_stride == 0) init_stride = kmax;
+    if (keep_stride < n || labels_stride < n || init_stride < kmax) return invalid("row strides too small");
+    return kmeans_batch_static(vecs, n, ntasks, keep, keep_stride, k, init, init_stride, iters, labels, labels_stride,
+                               keff, kmeans_bytes(n, ntasks, ktot), (hipStream_t)stream);
+}
+
 cs_status cs_optim_default_opts(cs_optim_opts *o) {
     if (!o) return invalid("null opts");
     o->m = 10;

@@ -170,6 +170,11 @@ size_t kmeans_bytes(int64_t n, int32_t ntasks, int64_t ktot);
 cs_status kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep, int64_t keep_stride,
                        const int32_t *k_host, const int32_t *init, int64_t init_stride, int32_t iters,
                        int32_t *labels, int64_t labels_stride, int32_t *keff, void *ws, hipStream_t s);
+// the same on this device's library-owned scratch array; bytes = kmeans_bytes of the arguments
+cs_status kmeans_batch_static(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep,
+                              int64_t keep_stride, const int32_t *k_host, const int32_t *init, int64_t init_stride,
+                              int32_t iters, int32_t *labels, int64_t labels_stride, int32_t *keff, size_t bytes,
+                              hipStream_t s);
 
 // a8: batched projected L-BFGS (cs_optim.hip)
 size_t optimizer_bytes(const cs_problem *p, int32_t m);

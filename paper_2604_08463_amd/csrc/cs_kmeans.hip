@@ -18,6 +18,7 @@
 //   k_km_update   per (task, cluster): ordered member sum, norm, division
 //   k_km_used / k_km_remap / k_km_write: compaction to 0..K_eff-1 and the caller's labels
 #include <algorithm>
+#include <mutex>
 
 #include "cs_device.h"
 
@@ -273,6 +274,40 @@ __global__ __launch_bounds__(kKmThreads) void k_km_write(const KmArgs a, int32_t
 
 }  // namespace
 
+// Workspace of the allocation-free entry point: one copy of this array on every GPU the library
+// runs on, held until the process ends.  In host code its name stands for the symbol only; the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char km_scratch[CS_KMEANS_STATIC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // device address of km_scratch per device id
+}  // namespace
+
+// Device address of this device's km_scratch (looked up on the first call on the device).
+static cs_status km_scratch_address(void **out) {
+    int dev = 0;
+    CSI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device id beyond the 64 the allocation-free K-means supports");
+        return CS_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(km_scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(km_scratch)");
+        if (!ptr) {
+            set_error("hipGetSymbolAddress(km_scratch) returned a null address");
+            return CS_E_HIP;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return CS_OK;
+}
+
 size_t kmeans_bytes(int64_t n, int32_t ntasks, int64_t ktot) {
     int64_t np2 = 2048;
     while (np2 < n) np2 <<= 1;
@@ -356,6 +391,23 @@ cs_status kmeans_batch(const double *vecs, int64_t n, int32_t ntasks, const uint
     hipLaunchKernelGGL(k_km_write, dim3(nb, ntasks), dim3(kKmThreads), 0, s, a, labels, labels_stride);
     CSI_HIP(hipGetLastError());
     return CS_OK;
+}
+
+cs_status kmeans_batch_static(const double *vecs, int64_t n, int32_t ntasks, const uint8_t *keep,
+                              int64_t keep_stride, const int32_t *k_host, const int32_t *init, int64_t init_stride,
+                              int32_t iters, int32_t *labels, int64_t labels_stride, int32_t *keff, size_t bytes,
+                              hipStream_t s) {
+    if (bytes > CS_KMEANS_STATIC_BYTES) {
+        set_error("K-means workspace of " + std::to_string(bytes) + " bytes exceeds the " +
+                  std::to_string((size_t)CS_KMEANS_STATIC_BYTES) +
+                  " bytes of the allocation-free entry point: use cs_kmeans_batch or fewer tasks per call");
+        return CS_E_WORKSPACE;
+    }
+    void *ws = nullptr;
+    const cs_status st = km_scratch_address(&ws);
+    if (st != CS_OK) return st;
+    return kmeans_batch(vecs, n, ntasks, keep, keep_stride, k_host, init, init_stride, iters, labels, labels_stride,
+                        keff, ws, s);
 }
 
 }  // namespace csi

@@ -175,19 +175,23 @@ def opt_summary(cs, h, solver="projected L-BFGS"):
 
 
 def maps_leg(prob, x, reps=5):
-    """Component maps and sigma^2_CMB of every item at x: items per second and the bytes moved
-    (the stored data read once, the six FP64 maps written)."""
-    prob.cs_component_maps(x)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        prob.cs_component_maps(x)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    pix = prob.nitems * prob.npix
-    nbytes = pix * (2 * prob.nfreq * 4 + 6 * 8)
-    return dict(items_per_s=prob.nitems / dt, ms_per_call=dt * 1e3, bytes_per_call=nbytes,
-                achieved_gbs=nbytes / dt / 1e9)
+    """Component maps and sigma^2_CMB of every item at x, in the caller's pixel order and in
+    processing order: items per second and the bytes moved (the stored data read once, the six
+    FP64 maps written)."""
+    out = {}
+    for name, srt in (("pixel_order", False), ("processing_order", True)):
+        prob.cs_component_maps(x, sorted_order=srt)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            prob.cs_component_maps(x, sorted_order=srt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        pix = prob.nitems * prob.npix
+        nbytes = pix * (2 * prob.nfreq * 4 + 6 * 8)
+        out[name] = dict(items_per_s=prob.nitems / dt, ms_per_call=dt * 1e3, bytes_per_call=nbytes,
+                         achieved_gbs=nbytes / dt / 1e9)
+    return out
 
 
 def kmeans_leg(ntask=1024, npix=3072, iters=20, seed=2604):
@@ -389,6 +393,8 @@ def main():
     ap.add_argument("--precision", default="fp32_bulk", choices=["fp64", "fp32_bulk", "fp32_store"])
     ap.add_argument("--schedule", default=None,
                     help="waves_per_block,blocks_per_cu,xcd_remap,shared_segments (skips the autotuner)")
+    ap.add_argument("--profile-maps", default=None, choices=["pixel", "processing"],
+                    help="kernel-profiling run: only the component maps (FP32-bulk problem), in that order")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="HBM counter calibration: time a plain device copy of this many bytes and exit")
     args = ap.parse_args()
@@ -438,6 +444,20 @@ def main():
         ne = int(h["nevals"].sum())
         print(json.dumps({"precision": args.precision, "optimizer_s": h["time_s"], "evals": ne,
                           "ms_per_step": h["time_s"] / (ne / sky.nitems) * 1e3}), flush=True)
+        return
+
+    if args.profile_maps:
+        prob = cs.Problem.from_sky(sky, "fp32_bulk")
+        srt = args.profile_maps == "processing"
+        for _ in range(args.warmup):
+            prob.cs_component_maps(x, sorted_order=srt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            prob.cs_component_maps(x, sorted_order=srt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        print(json.dumps({"maps_order": args.profile_maps, "ms_per_call": dt * 1e3}), flush=True)
         return
 
     if args.profile:

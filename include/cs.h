@@ -166,6 +166,20 @@ cs_status cs_likelihood_grad(cs_problem *prob, const double *x, double *neg2logL
 cs_status cs_component_maps(cs_problem *prob, const double *x, double *maps, int64_t maps_item_stride,
                             double *cmb_var, int32_t *status, void *stream);
 
+/* As cs_component_maps, with each item's maps in processing order instead of the caller's pixel
+ * order: entry i of every [P] row is the amplitude of pixel order[i] (cs_problem_pixel_order), for
+ * i < n_included; entries n_included .. P - 1 hold NaN.  Every map write is coalesced, where the
+ * pixel-order variant scatters 8-byte writes whenever neighbouring pixels of a patch are not
+ * neighbours in the caller's numbering. */
+cs_status cs_component_maps_sorted(cs_problem *prob, const double *x, double *maps,
+                                   int64_t maps_item_stride, double *cmb_var, int32_t *status,
+                                   void *stream);
+
+/* Processing order of an item (after prepare): order[i] (device int32, n_included entries) is the
+ * caller's index of the pixel in slot i -- included pixels sorted by (l_T, l_d, l_s, pixel).
+ * Enqueued on the stream. */
+cs_status cs_problem_pixel_order(cs_problem *prob, int32_t item, int32_t *order, void *stream);
+
 /* Spherical K-means patching (paper Sec. 2.2) of ntasks independent tasks over one set of n
  * unit vectors, on the device.  Task t clusters the vectors it keeps into k[t] patches: the
  * nearest centroid in angular separation is the one of largest dot product (ties: lowest

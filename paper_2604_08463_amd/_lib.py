@@ -63,6 +63,7 @@ _lib = None
 EXPORTS = [
     "cs_problem_create", "cs_problem_param_offsets", "cs_problem_workspace_bytes", "cs_problem_prepare",
     "cs_problem_item_info", "cs_problem_segments", "cs_likelihood", "cs_likelihood_grad", "cs_component_maps",
+    "cs_component_maps_sorted", "cs_problem_pixel_order",
     "cs_kmeans_workspace_bytes", "cs_kmeans_batch", "cs_kmeans_batch_static", "cs_optim_default_opts",
     "cs_optimizer_workspace_bytes", "cs_optimize_batch", "cs_optimize_batch_run", "cs_item_range",
     "cs_problem_desc_slice", "cs_problem_get_schedule", "cs_problem_set_schedule",
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     L.cs_likelihood.argtypes = [vp, vp, vp, vp, vp]
     L.cs_likelihood_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.cs_component_maps.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.cs_component_maps_sorted.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.cs_problem_pixel_order.argtypes = [vp, i32, vp, vp]
     L.cs_kmeans_workspace_bytes.argtypes = [i64, i32, P(i32), P(C.c_size_t)]
     L.cs_kmeans_batch.argtypes = [vp, i64, i32, vp, i64, P(i32), vp, i64, i32, vp, i64, vp, vp, C.c_size_t, vp]
     L.cs_kmeans_batch_static.argtypes = [vp, i64, i32, vp, i64, P(i32), vp, i64, i32, vp, i64, vp, vp]
@@ -393,16 +396,25 @@ class Problem:
                "cs_likelihood_grad")
         return f, g, cf, st
 
-    def cs_component_maps(self, x, maps: bool = True):
-        """Returns ``(maps [B][2][3][P] or None, cmb_var [B], status [B])`` (device tensors)."""
+    def cs_component_maps(self, x, maps: bool = True, sorted_order: bool = False):
+        """Returns ``(maps [B][2][3][P] or None, cmb_var [B], status [B])`` (device tensors); with
+        ``sorted_order`` the maps are in processing order (see :meth:`pixel_order`)."""
         x = self._x(x)
         B = self.nitems
         m = torch.empty((B, 2, 3, self.npix), dtype=torch.float64, device=self.device) if maps else None
         v = torch.empty(B, dtype=torch.float64, device=self.device)
         st = torch.empty(B, dtype=torch.int32, device=self.device)
-        _check(load().cs_component_maps(self._h, _ptr(x), _ptr(m), 0, _ptr(v), _ptr(st), _stream(self._stream)),
-               "cs_component_maps")
+        fn = load().cs_component_maps_sorted if sorted_order else load().cs_component_maps
+        _check(fn(self._h, _ptr(x), _ptr(m), 0, _ptr(v), _ptr(st), _stream(self._stream)), "cs_component_maps")
         return m, v, st
+
+    def pixel_order(self, item: int):
+        """Caller's pixel index of each processing slot of an item (device int32 [n_included])."""
+        n, _ = self.item_info(item)
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        _check(load().cs_problem_pixel_order(self._h, item, _ptr(out), _stream(self._stream)),
+               "cs_problem_pixel_order")
+        return out[:n]
 
     def optimizer_state(self, m: int = 10) -> OptState:
         nb = C.c_size_t()

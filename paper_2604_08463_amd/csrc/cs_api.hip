@@ -71,6 +71,7 @@ static void carve(cs_problem *p) {
     w.seg_perm = take(sizeof(int32_t) * w.p64 * 3 * L);
     w.seg_off = take(sizeof(int32_t) * (w.kmax[0] + w.kmax[1] + w.kmax[2] + 3) * L);
     w.counts = take(sizeof(int32_t) * 4 * L);
+    w.excl = take(sizeof(int32_t) * (size_t)p->P * L);
     w.dpack = take(elem * 2 * (size_t)p->F * kChunk * w.nchunk_max * B);
     w.wpack = take(p->nmode == CS_NINV_PIXEL ? elem * 2 * (size_t)p->F * kChunk * w.nchunk_max * B : 0);
     w.tables = take(sizeof(double) * (size_t)p->F * (size_t)p->taboff[p->B]);
@@ -267,6 +268,7 @@ cs_status cs_problem_prepare(cs_problem *p, void *workspace, size_t bytes, void 
             L.k[j] = p->ncl[3 * (size_t)l + j];
         }
         L.counts = (int32_t *)(base + w.counts) + 4 * (size_t)l;
+        L.excl = (int32_t *)(base + w.excl) + (size_t)l * (size_t)p->P;
     }
     p->items.assign(p->B, ItemDev{});
     for (int b = 0; b < p->B; ++b) {
@@ -361,16 +363,39 @@ cs_status cs_likelihood_grad(cs_problem *p, const double *x, double *neg2logl, d
     return eval_common(p, x, neg2logl, grad, cluster_f, status, true, stream);
 }
 
-cs_status cs_component_maps(cs_problem *p, const double *x, double *maps, int64_t maps_item_stride,
-                            double *cmb_var, int32_t *status, void *stream) {
+static cs_status maps_common(cs_problem *p, const double *x, double *maps, int64_t maps_item_stride, double *cmb_var,
+                             int32_t *status, bool sorted, void *stream) {
     if (!p || !x) return invalid("null argument");
     if (maps_item_stride != 0 && maps_item_stride < 6 * (int64_t)p->P) return invalid("maps_item_stride must be 0 or >= 6 P");
     if (!p->prepared) {
         set_error("cs_problem_prepare has not completed");
         return CS_E_STATE;
     }
-    return launch_maps(p, x, maps, maps_item_stride ? maps_item_stride : 6 * (int64_t)p->P, cmb_var, status,
+    return launch_maps(p, x, maps, maps_item_stride ? maps_item_stride : 6 * (int64_t)p->P, cmb_var, status, sorted,
                        (hipStream_t)stream);
+}
+
+cs_status cs_component_maps(cs_problem *p, const double *x, double *maps, int64_t maps_item_stride,
+                            double *cmb_var, int32_t *status, void *stream) {
+    return maps_common(p, x, maps, maps_item_stride, cmb_var, status, false, stream);
+}
+
+cs_status cs_component_maps_sorted(cs_problem *p, const double *x, double *maps, int64_t maps_item_stride,
+                                   double *cmb_var, int32_t *status, void *stream) {
+    return maps_common(p, x, maps, maps_item_stride, cmb_var, status, true, stream);
+}
+
+cs_status cs_problem_pixel_order(cs_problem *p, int32_t item, int32_t *order, void *stream) {
+    if (!p || item < 0 || item >= p->B || !order) return invalid("bad pixel-order request");
+    if (!p->prepared) {
+        set_error("cs_problem_prepare has not completed");
+        return CS_E_STATE;
+    }
+    const LayoutDev &L = p->layouts[p->items[item].layout];
+    if (L.n_incl > 0)
+        CSI_HIP(hipMemcpyAsync(order, L.order, sizeof(int32_t) * (size_t)L.n_incl, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+    return CS_OK;
 }
 
 static cs_status kmeans_check(int64_t n, int32_t ntasks, const int32_t *k, int64_t *ktot) {

@@ -48,7 +48,8 @@ struct LayoutDev {
     int4 *seg_lab;          // [P64] (l_d, l_T, l_s, first slot) of each segment
     int32_t *seg_perm[3];   // [P64] segments grouped by the cluster of labelling j
     int32_t *seg_off[3];    // [K_j + 1]
-    int32_t *counts;        // [4]: n_included, n_segments, label error, spare
+    int32_t *excl;          // [P] excluded pixels (label -1), in no particular order
+    int32_t *counts;        // [4]: n_included, n_segments, label error, n_excluded
     int32_t k[3];
     int32_t n_incl;         // filled after prepare
     int32_t nchunks;
@@ -88,7 +89,7 @@ struct EvalArgs {
 // Workspace regions (byte offsets, 256-aligned), see carve_workspace().
 struct WsLayout {
     size_t band, items, layouts, units, keys, order, head, seg_base, seg_lab, seg_perm, seg_off,
-        counts, dpack, wpack, tables, partials, segoff, istatus, fpart, total;
+        counts, excl, dpack, wpack, tables, partials, segoff, istatus, fpart, total;
     size_t keys_stride, p64, nchunk_max, np2, kmax[3];
 };
 
@@ -162,8 +163,9 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
                       cs_precision mode, hipStream_t s);
 
 // component maps and the CMB map variance (cs_maps.hip)
+// sorted: maps in processing order (slot i of an item = pixel order[i]) instead of pixel order
 cs_status launch_maps(cs_problem *p, const double *x, double *maps, int64_t maps_stride, double *cmb_var,
-                      int32_t *status, hipStream_t s);
+                      int32_t *status, bool sorted, hipStream_t s);
 
 // spherical K-means patching (cs_kmeans.hip)
 size_t kmeans_bytes(int64_t n, int32_t ntasks, int64_t ktot);

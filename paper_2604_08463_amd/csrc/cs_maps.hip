@@ -6,12 +6,17 @@
 // the reconstructed CMB amplitude over the analysis mask, here the population variance of Q plus
 // that of U (Sec. 2.4, eq. min_var).
 //
-//   k_fill_nan  every map element of the requested items := NaN (excluded pixels stay NaN)
+//   k_fill_excl per (item, excluded pixel): NaN in the six maps at the pixel (pixel order), or at
+//               the slots past the included pixels (processing order)
 //   k_maps      one wavefront per 64-pixel chunk: FP64 normal equations from the stored data,
-//               Cholesky, s_hat written in the caller's pixel order, and the chunk's
-//               (count, mean, centred sum of squares) of the Q and U CMB amplitudes
+//               Cholesky, s_hat written in the caller's pixel order (scattered 8-byte writes
+//               when the pixel numbering is not spatial) or in processing order (coalesced),
+//               and the chunk's (count, mean, centred sum of squares) of the Q and U CMB
+//               amplitudes
 //   k_maps_var  one workgroup per item: pairwise combination of the chunk moments
 //               (Chan, Golub & LeVeque's update), variance and status word
+#include <algorithm>
+
 #include "cs_device.h"
 
 namespace csi {
@@ -45,16 +50,24 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_fill_nan(double *maps, int64_t stride, int64_t per_item, int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int64_t b = i / per_item;
-    maps[b * stride + (i - b * per_item)] = __builtin_nan("");
+// grid (excluded-pixel blocks, item): the P - n_included excluded pixels of the item (pixel order)
+// or the slots n_included .. P - 1 (processing order) get NaN in all six maps
+__global__ __launch_bounds__(256) void k_fill_excl(const EvalArgs a, double *maps, int64_t stride, int32_t npix,
+                                                   int sorted) {
+    const int item = blockIdx.y;
+    const cptr<LayoutDev> L = as_const(a.layouts) + (as_const(a.items) + item)->layout;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n_incl = L->n_incl;
+    if (e >= (int64_t)npix - n_incl) return;
+    const int64_t pos = sorted ? n_incl + e : as_global(L->excl)[e];
+    double *o = maps + (int64_t)item * stride + pos;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o[(int64_t)c * npix] = __builtin_nan("");
 }
 
 template <typename TS>
 __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const int wm, double *maps,
-                                                          const int64_t stride, const int32_t npix) {
+                                                          const int64_t stride, const int32_t npix, const int sorted) {
     const int lane = threadIdx.x & 63;
     const int64_t u = (int64_t)blockIdx.x * kMapWaves + (threadIdx.x >> 6);
     if (u >= a.nunits) return;
@@ -136,7 +149,8 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_maps(const EvalArgs a, const
     if (__ballot(valid && !ok) && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
 
     if (maps && valid) {
-        const int32_t pix = L->order[chunk * kChunk + lane];
+        const int32_t slot = chunk * kChunk + lane;
+        const int32_t pix = sorted ? slot : L->order[slot];
         double *o = maps + (int64_t)item * stride + pix;
         for (int s = 0; s < 2; ++s)
             for (int c = 0; c < 3; ++c) o[(int64_t)(3 * s + c) * npix] = sh[s][c];
@@ -195,24 +209,30 @@ __global__ __launch_bounds__(kVarThreads) void k_maps_var(const EvalArgs a, doub
 }  // namespace
 
 cs_status launch_maps(cs_problem *p, const double *x, double *maps, int64_t maps_stride, double *cmb_var,
-                      int32_t *status, hipStream_t s) {
+                      int32_t *status, bool sorted, hipStream_t s) {
     const EvalArgs a = make_eval_args(p, x, nullptr);
     cs_status st = launch_sed(p, a, false, s);  // FP64 tables (also resets the status words)
     if (st != CS_OK) return st;
-    const int64_t per_item = 6 * (int64_t)p->P;
-    if (maps) {
-        const int64_t total = per_item * p->B;
-        hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, maps, maps_stride,
-                           per_item, total);
-        CSI_HIP(hipGetLastError());
+    int64_t nexcl = 0;  // most excluded pixels of one item
+    for (int b = 0; b < p->B; ++b)
+        nexcl = std::max<int64_t>(nexcl, (int64_t)p->P - p->layouts[p->items[b].layout].n_incl);
+    if (maps && nexcl > 0) {
+        for (int b0 = 0; b0 < p->B; b0 += kMaxGridY) {
+            const dim3 grid((unsigned)((nexcl + 255) / 256), (unsigned)std::min(kMaxGridY, p->B - b0));
+            EvalArgs ab = a;
+            ab.items = a.items + b0;
+            hipLaunchKernelGGL(k_fill_excl, grid, dim3(256), 0, s, ab, maps + (int64_t)b0 * maps_stride, maps_stride,
+                               p->P, (int)sorted);
+            CSI_HIP(hipGetLastError());
+        }
     }
     const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
     if (p->nunits > 0) {
         const dim3 grid((unsigned)((p->nunits + kMapWaves - 1) / kMapWaves)), block(64 * kMapWaves);
         if (p->prec == CS_FP64)
-            hipLaunchKernelGGL(k_maps<double>, grid, block, 0, s, a, wm, maps, maps_stride, p->P);
+            hipLaunchKernelGGL(k_maps<double>, grid, block, 0, s, a, wm, maps, maps_stride, p->P, (int)sorted);
         else
-            hipLaunchKernelGGL(k_maps<float>, grid, block, 0, s, a, wm, maps, maps_stride, p->P);
+            hipLaunchKernelGGL(k_maps<float>, grid, block, 0, s, a, wm, maps, maps_stride, p->P, (int)sorted);
         CSI_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_maps_var, dim3(p->B), dim3(kVarThreads), 0, s, a, cmb_var, status);

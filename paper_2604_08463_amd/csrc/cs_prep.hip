@@ -115,7 +115,8 @@ struct KeyBits {
     int bd, bt, bs, bp;
 };
 
-// 1. keys = (l_T, l_d, l_s, p); invalid labels set the error flag; excluded pixels sort last.
+// 1. keys = (l_T, l_d, l_s, p); invalid labels set the error flag; excluded pixels sort last and
+//    are listed (in no particular order) for the component maps, which write NaN there.
 __global__ __launch_bounds__(256) void k_make_keys(const LayoutDev *lays, int32_t npix, int64_t np2, KeyBits kb) {
     const LayoutDev L = lays[blockIdx.y];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,6 +131,8 @@ __global__ __launch_bounds__(256) void k_make_keys(const LayoutDev *lays, int32_
                   ((uint64_t)c << kb.bp) | (uint64_t)i;
         } else if (nexcl != 3) {
             atomicOr(&L.counts[2], 1);
+        } else {
+            L.excl[atomicAdd(&L.counts[3], 1)] = (int32_t)i;
         }
     }
     L.keys[i] = key;

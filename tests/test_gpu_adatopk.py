@@ -101,10 +101,26 @@ def test_adatopk_workload3_items_reach_lbfgs_optimum():
     _log(f"  F adatopk {np.array2string(np.asarray(r['f']), precision=10)}")
     _log(f"  F lbfgs   {np.array2string(f_l, precision=10)}")
     assert np.all(r["status"] & cs.CONVERGED)
-    # both reach the same minimum of -2 ln L.  Several of these items have beta_s at its bound
-    # (no synchrotron signal), which leaves the minimum flat along T_d, so the two optimisers'
-    # points can lie apart on that flat valley at equal F: the values are what is compared.
+    # both optimisers reach the same minimum: the same F and the same parameters, and the AdaTopK
+    # point is a converged point of the oracle's objective.  (The objective can have several
+    # local minima; any gap would show here as a failure, not be asserted away.)
+    dx = np.abs(r["x"] - x_l) / np.maximum(1.0, np.abs(x_l))
+    _log(f"  max |x_adatopk - x_lbfgs| / max(1, |x|) {dx.max():.2e}")
     assert np.all(np.abs(r["f"] - f_l) <= 1e-10 * np.abs(f_l))
+    assert np.all(dx <= 1e-4)
+    for b in range(sky.nitems):
+        po = oracle.Problem.from_sky(sky, b)
+        sl = slice(3 * b, 3 * b + 3)
+        _, g, _, _ = po.likelihood_grad(r["x"][sl])
+        _, g0, _, _ = po.likelihood_grad(sky.x[b])
+        w = hi[sl] - lo[sl]
+        y = (r["x"][sl] - lo[sl]) / w
+
+        def pg(gg, yy):
+            gi = gg * w
+            return np.linalg.norm(np.where(((yy <= 0) & (gi > 0)) | ((yy >= 1) & (gi < 0)), 0.0, gi))
+
+        assert pg(g, y) <= 2e-8 * pg(g0, (sky.x[b] - lo[sl]) / w), b
 
 
 @pytest.mark.parametrize("kd", [300, 1500])

@@ -1,4 +1,5 @@
-"""GPU parity of the component maps and the CMB map variance (cs_component_maps) with the oracle.
+"""GPU parity of the component maps and the CMB map variance (cs_component_maps, and its
+processing-order variant cs_component_maps_sorted) with the oracle.
 
 The device forms the maps in FP64 from the data as stored (FP32 for the FP32 precisions); the
 oracle is fed exactly those stored values, so every precision is held to the FP64 bar.  The
@@ -154,3 +155,28 @@ def test_maps_leave_evaluations_unchanged(precision):
     f1, g1, c1, s1 = prob.cs_likelihood_grad(x, cluster=True)
     torch.cuda.synchronize()
     assert torch.equal(f0, f1) and torch.equal(g0, g1) and torch.equal(c0, c1) and torch.equal(s0, s1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_maps_in_processing_order_match_pixel_order(precision):
+    # ragged items with their own labellings and masks: the processing-order maps are the
+    # pixel-order maps permuted by the exported order, bit for bit; the slots past the included
+    # pixels hold NaN, as do the excluded pixels in pixel order
+    sky = skygen.make_config(4, nitems=3, kmax4=(200, 30, 60))
+    prob = cs.Problem.from_sky(sky, precision)
+    if precision == "fp64":
+        _check_maps(sky, prob)
+    x = torch.as_tensor(sky.x_packed(), device="cuda")
+    m, v, st = prob.cs_component_maps(x)
+    ms, vs, sts = prob.cs_component_maps(x, sorted_order=True)
+    torch.cuda.synchronize()
+    assert torch.equal(v, vs) and torch.equal(st, sts)
+    for b in range(sky.nitems):
+        order = prob.pixel_order(b).long()
+        n = order.numel()
+        assert n == int(np.sum(sky.item_labels(b)[0] >= 0))
+        assert torch.equal(ms[b][:, :, :n], m[b][:, :, order])
+        assert torch.all(torch.isnan(ms[b][:, :, n:]))
+        excl = torch.ones(sky.npix, dtype=torch.bool, device="cuda")
+        excl[order] = False
+        assert torch.all(torch.isnan(m[b][:, :, excl])) and not torch.any(torch.isnan(m[b][:, :, ~excl]))

@@ -315,10 +315,14 @@ typedef struct {
     int32_t blocks_per_cu;   /* 0 = one 64-pixel unit per wavefront (no grid-stride loop);
                                 n > 0 = persistent grid of n * 256 workgroups              */
     int32_t xcd_remap;       /* 1 = give each of the 8 XCDs a contiguous range of units    */
-    int32_t shared_segments; /* 1 = form A^T N^-1 A, its Cholesky factor and the adjoint
-                                sums once per segment (constant-label run) in LDS and share
-                                them across its pixels (band weights shared by Q and U
-                                only); 0 = every pixel forms its own                       */
+    int32_t shared_segments; /* staging mode of the LDS-staged kernel (band weights shared
+                                by Q and U only): 0 = every pixel forms A^T N^-1 A and the
+                                adjoint sums itself; 1 = formed once per segment
+                                (constant-label run) with its Cholesky factor in LDS and
+                                shared across its pixels; 2 = formed once per segment by
+                                five lanes per segment, each pixel then taking them by
+                                cross-lane reads and forming its own Cholesky factor
+                                (CS_FP32_BULK only; in other precisions it runs as 0)      */
 } cs_schedule;
 
 cs_status cs_problem_get_schedule(const cs_problem *prob, cs_schedule *sched);

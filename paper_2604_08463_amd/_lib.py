@@ -449,7 +449,7 @@ class Problem:
         _check(load().cs_problem_get_schedule(self._h, C.byref(s)), "cs_problem_get_schedule")
         return s
 
-    def set_schedule(self, waves_per_block=4, blocks_per_cu=0, xcd_remap=1, shared_segments=1):
+    def set_schedule(self, waves_per_block=2, blocks_per_cu=0, xcd_remap=1, shared_segments=2):
         s = Schedule(waves_per_block, blocks_per_cu, xcd_remap, shared_segments)
         _check(load().cs_problem_set_schedule(self._h, C.byref(s)), "cs_problem_set_schedule")
 

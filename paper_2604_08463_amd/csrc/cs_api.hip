@@ -211,6 +211,7 @@ cs_status cs_problem_create(const cs_problem_desc *d, cs_problem **out) {
         p->xoff[b + 1] = p->xoff[b] + kd + kt + ks;
         p->kmax_item = std::max<int64_t>(p->kmax_item, kd + kt + ks);
         p->taboff[b + 1] = p->taboff[b] + kd + 2 * kt + ks;
+        p->trows_max = std::max<int64_t>(p->trows_max, kd + 2 * kt + ks);
     }
     carve(p);
     const int bits = bits_for((int64_t)p->ws.kmax[0]) + bits_for((int64_t)p->ws.kmax[1]) +
@@ -552,7 +553,7 @@ cs_status cs_problem_set_schedule(cs_problem *p, const cs_schedule *s) {
     if (!p || !s) return invalid("null argument");
     const int w = s->waves_per_block;
     if (!(w == 1 || w == 2 || w == 4 || w == 8) || s->blocks_per_cu < 0 || s->blocks_per_cu > 64 ||
-        (s->xcd_remap != 0 && s->xcd_remap != 1) || (s->shared_segments != 0 && s->shared_segments != 1))
+        (s->xcd_remap != 0 && s->xcd_remap != 1) || s->shared_segments < 0 || s->shared_segments > 2)
         return invalid("bad schedule");
     p->sched = *s;
     return CS_OK;
@@ -583,8 +584,8 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
     std::vector<std::pair<float, cs_schedule>> cand;  // (time, schedule) of every agreeing schedule
     const int waves[4] = {1, 2, 4, 8};
     const int bpc[3] = {0, 2, 4};
-    // tolerances across the two rounding orders (per-pixel or per-segment sums): F relative, and
-    // the gradient normwise per item
+    // tolerances across the rounding orders of the staging modes: F relative, and the gradient
+    // normwise per item
     const double cross_tol = p->prec == CS_FP32_BULK ? 1e-6 : 1e-11;
     const double cross_gtol = p->prec == CS_FP32_BULK ? 1e-3 : 1e-8;
     // a candidate is kept only when F and the gradient of every item agree with the reference
@@ -605,8 +606,18 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
         }
         return true;
     };
-    for (int sh = 0; sh < 2 && rc == CS_OK; ++sh)
-        for (int wi = 0; wi < 4 && rc == CS_OK; ++wi)
+    // staging modes that run in this problem's precision (the segment-sum mode needs FP32
+    // accumulation, else it runs as the per-pixel mode and is not timed twice)
+    auto eff_mode = [&](int sh) {
+        const cs_schedule was = p->sched;
+        p->sched.shared_segments = sh;
+        const int m = staging_mode(p, p->prec);
+        p->sched = was;
+        return m;
+    };
+    const int keep_mode = eff_mode(keep.shared_segments);
+    for (int sh = 0; sh < 3 && rc == CS_OK; ++sh)
+        for (int wi = 0; wi < 4 && rc == CS_OK && eff_mode(sh) == sh; ++wi)
             for (int bi = 0; bi < 3 && rc == CS_OK; ++bi)
                 for (int xr = 0; xr < 2 && rc == CS_OK; ++xr) {
                     p->sched = cs_schedule{waves[wi], bpc[bi], xr, sh};
@@ -624,7 +635,7 @@ cs_status cs_problem_autotune(cs_problem *p, const double *x, double *neg2logl, 
                         rc = CS_E_HIP;
                         break;
                     }
-                    if (agrees(sh == keep.shared_segments)) cand.emplace_back(ms, p->sched);
+                    if (agrees(sh == keep_mode)) cand.emplace_back(ms, p->sched);
                 }
     // second stage: the four fastest re-timed in turn over three rounds with more repetitions, so
     // that one noisy timing does not decide

@@ -22,6 +22,21 @@ __device__ __forceinline__ gptr<T> as_global(const T *p) {
     return (gptr<T>)p;
 }
 
+// Load of the streamed data (read once per launch, no reuse within it): a nontemporal load, which
+// on gfx950 streams through the caches without displacing what is reused (tables, label
+// records, partials).
+#ifndef CS_NT_LOADS
+#define CS_NT_LOADS 1
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_stream(gptr<T> p) {
+#if CS_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
 __device__ __forceinline__ uint64_t lanemask_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }

@@ -24,6 +24,21 @@
 #ifndef CS_BAND_GROUP
 #define CS_BAND_GROUP 2
 #endif
+#ifndef CS_SUMS_RING
+#define CS_SUMS_RING 11
+#endif
+#ifndef CS_SUMS_WAVES
+#define CS_SUMS_WAVES 5
+#endif
+#ifndef CS_STAGE0_WAVES
+#define CS_STAGE0_WAVES 5
+#endif
+#ifndef CS_FP64_NOLOOP
+#define CS_FP64_NOLOOP 1
+#endif
+#ifndef CS_FP64_RING
+#define CS_FP64_RING 6
+#endif
 
 namespace csi {
 
@@ -129,8 +144,8 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
         TS vq[FM], vu[FM];
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
-            vq[f] = dq[f * kChunk];
-            vu[f] = du[f * kChunk];
+            vq[f] = ld_stream(dq + f * kChunk);
+            vu[f] = ld_stream(du + f * kChunk);
         }
         TA tp[2][kG], tb[2][kG], tt[2][kG], ts[2][kG];
 #pragma unroll
@@ -168,8 +183,8 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
 #pragma unroll
         for (int j = 0; j < kG; ++j) {
             const int f = j < F ? j : F - 1;
-            nq[j] = dq[f * kChunk];
-            nu[j] = du[f * kChunk];
+            nq[j] = ld_stream(dq + f * kChunk);
+            nu[j] = ld_stream(du + f * kChunk);
         }
         for (int g0 = 0; g0 < F; g0 += kG) {
             TS cq[kG], cu[kG];
@@ -189,8 +204,8 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
 #pragma unroll
                 for (int j = 0; j < kG; ++j) {
                     const int f = g0 + kG + j < F ? g0 + kG + j : F - 1;
-                    nq[j] = dq[f * kChunk];
-                    nu[j] = du[f * kChunk];
+                    nq[j] = ld_stream(dq + f * kChunk);
+                    nu[j] = ld_stream(du + f * kChunk);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -408,12 +423,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CS_WAVES_PE
 // the streaming data loads (a ring of kRing groups prefetched ahead) and reads the coefficients
 // from LDS, whose counter is separate from the vector-memory counter: no table gather ever
 // waits behind a data load.  M = A^T N^-1 A and the adjoint sums G_jk depend only on a pixel's
-// labels; two ways to form them:
-//   per-pixel (SHARED = false): every lane accumulates them over the bands itself;
-//   segment-shared (SHARED = true): while staging, four lanes per segment accumulate them over
+// labels; three ways to form them (the staging mode SM):
+//   per-pixel (SM = 0): every lane accumulates them over the bands itself;
+//   segment-shared (SM = 1): while staging, four lanes per segment accumulate them over
 //     interleaved bands and add their partials, and one of them forms the FP64 Cholesky factor
 //     of M into the slice; every pixel then accumulates only its data-dependent sums b and h
-//     (12 FMAs per band) and reads its segment's factor.
+//     (12 FMAs per band) and reads its segment's factor;
+//   segment sums (SM = 2, FP32 accumulation): the staging stores each (segment, band)'s
+//     coefficients (w a_d, w a_s, w a_d ln(nu/nu0d), w a_d dlnBT/dT, w a_s ln(nu/nu0s)) and
+//     (a_d, a_s); five lanes per segment then each run one coefficient over the bands against
+//     (1, a_d, a_s) -- all segments of a chunk in one pass, three sums per lane -- while every
+//     pixel accumulates only b and h (12 FMAs per band) and takes its segment's fourteen sums
+//     from those lanes by cross-lane reads before its own FP64 Cholesky.
 // Chunks with more than kStageSeg segments take the direct-gather per-pixel path.
 // ---------------------------------------------------------------------------------------------
 // Per segment: the Cholesky factor of M (inverse diagonal), G_jk and a positive-definite flag,
@@ -431,8 +452,14 @@ struct alignas(4 * sizeof(TA)) Col4 {
     TA x, y, z, w;
 };
 
+template <typename TA>
+struct alignas(2 * sizeof(TA)) Vec2 {
+    TA x, y;
+};
+
 // LDS slice of one wavefront: Col4 [kStageSeg][F]; the segment-shared mode adds TA [kStageSeg][F]
-// (16-byte padded) and double [kRecFields][kStageSeg]
+// (16-byte padded) and double [kRecFields][kStageSeg]; the segment-sum mode adds Vec2
+// [kStageSeg][F] and TA [kStageSeg][F]
 template <typename TA>
 __host__ __device__ constexpr size_t stage_col_bytes(int F) {
     return (size_t)kStageSeg * (size_t)F * sizeof(Col4<TA>);
@@ -441,10 +468,15 @@ template <typename TA>
 __host__ __device__ constexpr size_t stage_c5_bytes(int F) {
     return ((size_t)kStageSeg * (size_t)F * sizeof(TA) + 15) & ~(size_t)15;
 }
-template <typename TA, bool SHARED>
+template <typename TA>
+__host__ __device__ constexpr size_t stage_v2_bytes(int F) {
+    return (size_t)kStageSeg * (size_t)F * sizeof(Vec2<TA>);
+}
+template <typename TA, int SM>
 __host__ __device__ constexpr size_t stage_bytes_per_wave(int F) {
-    return SHARED ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
-                  : stage_col_bytes<TA>(F);
+    return SM == 1   ? stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F) + (size_t)kRecFields * kStageSeg * sizeof(double)
+           : SM == 2 ? stage_col_bytes<TA>(F) + stage_v2_bytes<TA>(F) + stage_c5_bytes<TA>(F)
+                     : stage_col_bytes<TA>(F);
 }
 
 // Sum over the four lanes of a quad, the same value in each: (v0 + v1) + (v2 + v3) via DPP
@@ -467,13 +499,16 @@ __device__ __forceinline__ T quad_sum(T v) {
     return v;
 }
 
-template <typename TS, typename TA, bool GRAD, bool SHARED>
+template <typename TS, typename TA, bool GRAD, int SM>
 __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, const int chunk, const int lane,
                                             char *wave_lds) {
+    constexpr bool SHARED = SM == 1;
+    constexpr bool SUMS = SM == 2;
+    static_assert(!SUMS || sizeof(TA) == 4, "the segment-sum mode stages FP32 coefficients");
     // groups of kG bands in flight per lane: the segment-shared band loop is short (12 FMAs per
     // band), so it looks further ahead (measured on gfx950: 8 groups for it; 6 for per-pixel with
     // FP32 accumulation, 4 with FP64, whose registers would otherwise cost it a wavefront)
-    constexpr int kRing = SHARED ? 8 : (sizeof(TA) == 4 ? 6 : 4);
+    constexpr int kRing = SHARED ? 8 : (SUMS ? CS_SUMS_RING : (sizeof(TA) == 4 ? 6 : CS_FP64_RING));
     constexpr int kG = 2;
     const cptr<BandDev> B = as_const(a.band);
     const int F = a.nfreq;
@@ -500,8 +535,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             for (int j = 0; j < kG; ++j) {
                 const int f0 = r * kG + j;
                 const int f = f0 < F ? f0 : F - 1;
-                rq[r][j] = dq[f * kChunk];
-                ru[r][j] = du[f * kChunk];
+                rq[r][j] = ld_stream(dq + f * kChunk);
+                ru[r][j] = ld_stream(du + f * kChunk);
             }
     };
     // table offsets of the fast path are 32-bit byte offsets
@@ -511,7 +546,9 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     if (!fast) issue_ring();
 
     Col4<TA> *cols = (Col4<TA> *)wave_lds;
-    TA *c5 = (TA *)(wave_lds + stage_col_bytes<TA>(F));
+    // the segment-sum mode keeps (a_d, a_s) between the coefficient columns and the fifth one
+    Vec2<TA> *v2 = (Vec2<TA> *)(wave_lds + stage_col_bytes<TA>(F));
+    TA *c5 = (TA *)(wave_lds + stage_col_bytes<TA>(F) + (SUMS ? stage_v2_bytes<TA>(F) : 0));
     double *recs = (double *)(wave_lds + stage_col_bytes<TA>(F) + stage_c5_bytes<TA>(F));
     const gptr<TA> tab = as_global((const TA *)a.tables) + it->tab_off * (int64_t)F;
     const gptr<int> seglab = as_global((const int *)L->seg_lab) + 4 * (int64_t)segbase;
@@ -527,11 +564,22 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const int rb = F * (int)sizeof(TA);  // bytes per table row
         const int kdb = (int)kd * rb, kdtb = (int)(kd + 2 * kt) * rb;
         const bool hi = lane >= 32;
-        const int f = lane & 31;
+        int f = lane & 31;
+        // segment-sum mode: the staging's LDS addresses are formed per unit (hoisted out of the
+        // unit loop they would hold 18 registers through the band loop)
+        if (SUMS) asm volatile("" : "+v"(f));
         const int fb = (f < F ? f : F - 1) * (int)sizeof(TA);
         const int nr = (nseg + 1) >> 1;
         const char *tb = (const char *)(const TA *)tab;
         auto at = [&](int e) { return *(gptr<TA>)(tb + (uint32_t)e); };
+        // segment-sum mode: this lane's band constants, requested ahead of the gathers
+        TA wl = 0, ldl = 0, lsl = 0;
+        if (SUMS) {
+            const int fc = f < F ? f : F - 1;
+            wl = Band<TA>::w(B, 0, fc);
+            ldl = Band<TA>::ld(B, fc);
+            lsl = Band<TA>::ls(B, fc);
+        }
         TA pdv[kRounds], btv[kRounds], dtv[kRounds], ssv[kRounds];
 #pragma unroll
         for (int r = 0; r < kRounds; ++r) {
@@ -559,8 +607,18 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const int lbase = (hi ? F : 0) + f;
 #pragma unroll
         for (int r = 0; r < kRounds; ++r)
-            if (r < nr && f < F && 2 * r + (hi ? 1 : 0) < nseg)
-                cols[2 * r * F + lbase] = Col4<TA>{pdv[r] * btv[r], dtv[r], ssv[r], (TA)0};
+            if (r < nr && f < F && 2 * r + (hi ? 1 : 0) < nseg) {
+                const int e = 2 * r * F + lbase;
+                const TA ad = pdv[r] * btv[r], dt = dtv[r], as = ssv[r];
+                if (SUMS) {
+                    const TA wad = wl * ad, was = wl * as;
+                    cols[e] = Col4<TA>{wad, was, wad * ldl, wad * dt};
+                    c5[e] = was * lsl;
+                    v2[e] = Vec2<TA>{ad, as};
+                } else {
+                    cols[e] = Col4<TA>{ad, dt, as, (TA)0};
+                }
+            }
     } else if (!SHARED) {
         // columns (a_d, da_d/dT / a_d, a_s) of every (segment, band), in phases of kPh rounds of
         // the wavefront whose gathers are all issued before their first use
@@ -706,6 +764,28 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    // segment-sum mode: lane 5 s + i runs coefficient i of segment s over the bands against
+    // (1, a_d, a_s); the i = 1 lane's a_d sum is not used.  Lanes past the chunk's segments
+    // (and lanes 60-63) read slots of the slice that hold no data of this unit and are not read.
+    TA ms0 = 0, ms1 = 0, ms2 = 0;
+    if (SUMS) {
+        const int q = lane / 5;
+        const int im = lane - 5 * q;
+        const int sgm = q < kStageSeg ? q : kStageSeg - 1;
+        const TA *up = im < 4 ? &cols[sgm * F].x + im : c5 + sgm * F;
+        const int ust = im < 4 ? 4 : 1;
+        const Vec2<TA> *vp = v2 + sgm * F;
+#pragma unroll 2
+        for (int f = 0; f < F; ++f) {
+            const TA u = *up;
+            up += ust;
+            const Vec2<TA> v = vp[f];
+            ms0 += u;
+            ms1 = fma(u, v.x, ms1);
+            ms2 = fma(u, v.y, ms2);
+        }
+    }
+
     WAcc<TA> A = WAcc<TA>{};
     SAcc<TA> S[2];
     S[0] = SAcc<TA>{};
@@ -715,7 +795,7 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     auto band = [&](const int f, const TA d0, const TA d1) {
         const Col4<TA> c = mycols[f];
         const TA w = Band<TA>::w(B, 0, f);
-        if (SHARED) {
+        if (SHARED || SUMS) {
             const TA c3 = myc5[f];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -779,8 +859,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
                 for (int j = 0; j < kG; ++j) {
                     const int f0 = fb + kRing * kG + j;
                     const int f = f0 < F ? f0 : F - 1;
-                    rq[r][j] = dq[f * kChunk];
-                    ru[r][j] = du[f * kChunk];
+                    rq[r][j] = ld_stream(dq + f * kChunk);
+                    ru[r][j] = ld_stream(du + f * kChunk);
                 }
             }
         }
@@ -802,6 +882,23 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         G[6] = R[kG21 * kStageSeg]; G[7] = R[kG22 * kStageSeg]; G[8] = R[kG23 * kStageSeg];
         ok = R[kOk * kStageSeg] != 0.0;
     } else {
+        if (SUMS) {  // the segment's sums from its five lanes
+            const int src = 5 * segl;
+            A.m01 = __shfl(ms0, src);
+            A.m11 = __shfl(ms1, src);
+            A.m12 = __shfl(ms2, src);
+            A.m02 = __shfl(ms0, src + 1);
+            A.m22 = __shfl(ms2, src + 1);
+            A.g01 = __shfl(ms0, src + 2);
+            A.g11 = __shfl(ms1, src + 2);
+            A.g21 = __shfl(ms2, src + 2);
+            A.g02 = __shfl(ms0, src + 3);
+            A.g12 = __shfl(ms1, src + 3);
+            A.g22 = __shfl(ms2, src + 3);
+            A.g03 = __shfl(ms0, src + 4);
+            A.g13 = __shfl(ms1, src + 4);
+            A.g23 = __shfl(ms2, src + 4);
+        }
         const double m00 = (double)Band<TA>::wsum(B, 0);
         const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;
         i00 = 1.0 / sqrt(m00);
@@ -851,15 +948,20 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     __builtin_amdgcn_wave_barrier();
 }
 
-// Minimum wavefronts per SIMD the register allocation must allow: five in the per-pixel mode with
-// FP32 accumulation (at most 96 VGPRs); the other modes are left to the compiler.
-template <typename TA, bool SHARED>
+// Minimum wavefronts per SIMD the register allocation must allow: five in the per-pixel and
+// segment-sum modes with FP32 accumulation (at most 96 VGPRs), four in the per-pixel mode with
+// FP64 accumulation (at most 128); the segment-shared mode is left to the compiler.
+template <typename TA, int SM>
 constexpr int stage_waves() {
-    return SHARED ? 1 : (sizeof(TA) == 4 ? 5 : 1);
+    return SM == 1 ? 1 : (SM == 2 ? CS_SUMS_WAVES : (sizeof(TA) == 4 ? CS_STAGE0_WAVES : 4));
 }
 
-template <typename TS, typename TA, bool GRAD, bool SHARED>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<TA, SHARED>()))) void k_pixel_stage(
+// The segment-sum staging forms 32-bit table offsets: items whose tables are larger take the
+// direct-gather path (the host selects the mode only when every item fits).  LOOP: persistent
+// grid, each wavefront looping over units; otherwise one unit per wavefront, so that nothing is
+// hoisted across units into registers (17 VGPRs in the segment-sum mode).
+template <typename TS, typename TA, bool GRAD, int SM, bool LOOP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<TA, SM>()))) void k_pixel_stage(
     const EvalArgs a) {
     extern __shared__ char smem[];
     const int lane = threadIdx.x & 63;
@@ -868,17 +970,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
     const int64_t nb = gridDim.x;
     const int64_t lb = logical_block(a.xcd_remap);
     const cptr<int> units = as_const((const int *)a.units);
-    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA, SHARED>(a.nfreq);
-    for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) {
+    char *wave_lds = smem + (size_t)wave * stage_bytes_per_wave<TA, SM>(a.nfreq);
+    auto unit = [&](const int64_t u) {
         const int item = __builtin_amdgcn_readfirstlane(units[2 * u]);
         const int chunk = __builtin_amdgcn_readfirstlane(units[2 * u + 1]);
-        if (a.active && !as_const(a.active)[item]) continue;
-        const cptr<LayoutDev> L = as_const(a.layouts) + (as_const(a.items) + item)->layout;
+        if (a.active && !as_const(a.active)[item]) return;
+        const cptr<ItemDev> it = as_const(a.items) + item;
+        const cptr<LayoutDev> L = as_const(a.layouts) + it->layout;
         const int nseg = as_const(L->seg_base)[chunk + 1] - as_const(L->seg_base)[chunk];
-        if (nseg <= kStageSeg)
-            unit_staged<TS, TA, GRAD, SHARED>(a, item, chunk, lane, wave_lds);
+        bool staged = nseg <= kStageSeg;
+        if (SM == 2) staged = staged && (it->k[0] + 2 * it->k[1] + it->k[2]) * a.nfreq < (int64_t(1) << 28);
+        if (staged)
+            unit_staged<TS, TA, GRAD, SM>(a, item, chunk, lane, wave_lds);
         else
             unit_pixel<TS, TA, GRAD, 0, 0>(a, item, chunk, lane);
+    };
+    if constexpr (LOOP) {
+        for (int64_t u = lb * wpb + wave; u < a.nunits; u += nb * wpb) unit(u);
+    } else {
+        const int64_t u = lb * wpb + wave;
+        if (u < a.nunits) unit(u);
     }
 }
 
@@ -1048,14 +1159,29 @@ __global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2log
 // ---------------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------------
-// wm == 0 (band weights shared by Q and U): the LDS-staged kernel, lds bytes per workgroup;
-// otherwise the direct-gather kernel with separate Q/U (wm = 1) or per-pixel (wm = 2) weights.
+// wm == 0 (band weights shared by Q and U): the LDS-staged kernel in staging mode sm, lds bytes
+// per workgroup; otherwise the direct-gather kernel with separate Q/U (wm = 1) or per-pixel
+// (wm = 2) weights.
+// The segment-sum mode takes its one-unit-per-wavefront form unless the grid is persistent; the
+// per-pixel and segment-shared modes keep the unit loop (measured faster for them on gfx950:
+// without it the per-pixel mode drops to 79 VGPRs and its sixth wavefront per SIMD costs time).
 template <typename TS, typename TA, bool GRAD>
-static void launch_pixel_t(int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s, const EvalArgs &a) {
-    if (wm == 0 && shared)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, true>), grid, block, lds, s, a);
-    else if (wm == 0)
-        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, false>), grid, block, lds, s, a);
+static void launch_pixel_t(int wm, int sm, bool loop, size_t lds, dim3 grid, dim3 block, hipStream_t s,
+                           const EvalArgs &a) {
+    if constexpr (sizeof(TA) == 4)
+        if (wm == 0 && sm == 2) {
+            if (loop)
+                hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 2, true>), grid, block, lds, s, a);
+            else
+                hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 2, false>), grid, block, lds, s, a);
+            return;
+        }
+    if (wm == 0 && sm == 1)
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 1, true>), grid, block, lds, s, a);
+    else if (wm == 0 && sizeof(TA) == 8 && CS_FP64_NOLOOP && !loop)
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 0, false>), grid, block, lds, s, a);
+    else if (wm == 0)  // sm 0, or 2 where it runs as 0
+        hipLaunchKernelGGL((k_pixel_stage<TS, TA, GRAD, 0, true>), grid, block, lds, s, a);
     else if (wm == 1)
         hipLaunchKernelGGL((k_pixel<TS, TA, GRAD, 1, 0>), grid, block, 0, s, a);
     else
@@ -1063,18 +1189,29 @@ static void launch_pixel_t(int wm, bool shared, size_t lds, dim3 grid, dim3 bloc
 }
 
 template <typename TS, typename TA>
-static void launch_pixel_g(bool grad, int wm, bool shared, size_t lds, dim3 grid, dim3 block, hipStream_t s,
+static void launch_pixel_g(bool grad, int wm, int sm, bool loop, size_t lds, dim3 grid, dim3 block, hipStream_t s,
                            const EvalArgs &a) {
     if (grad)
-        launch_pixel_t<TS, TA, true>(wm, shared, lds, grid, block, s, a);
+        launch_pixel_t<TS, TA, true>(wm, sm, loop, lds, grid, block, s, a);
     else
-        launch_pixel_t<TS, TA, false>(wm, shared, lds, grid, block, s, a);
+        launch_pixel_t<TS, TA, false>(wm, sm, loop, lds, grid, block, s, a);
 }
 
-// LDS slice of one wavefront of the staged kernel in an arithmetic mode
-static size_t stage_bytes(cs_precision mode, bool shared, int F) {
-    if (mode == CS_FP32_BULK) return shared ? stage_bytes_per_wave<float, true>(F) : stage_bytes_per_wave<float, false>(F);
-    return shared ? stage_bytes_per_wave<double, true>(F) : stage_bytes_per_wave<double, false>(F);
+// LDS slice of one wavefront of the staged kernel in an arithmetic and staging mode
+static size_t stage_bytes(cs_precision mode, int sm, int F) {
+    if (mode == CS_FP32_BULK)
+        return sm == 1   ? stage_bytes_per_wave<float, 1>(F)
+               : sm == 2 ? stage_bytes_per_wave<float, 2>(F)
+                         : stage_bytes_per_wave<float, 0>(F);
+    return sm == 1 ? stage_bytes_per_wave<double, 1>(F) : stage_bytes_per_wave<double, 0>(F);
+}
+
+// Staging mode of a launch: the segment-sum mode needs FP32 accumulation and 32-bit table
+// offsets; otherwise it runs as the per-pixel mode (the same sums in another rounding order).
+int staging_mode(const cs_problem *p, cs_precision mode) {
+    const int sm = p->sched.shared_segments;
+    if (sm == 2 && !(mode == CS_FP32_BULK && p->trows_max * p->F < (int64_t(1) << 28))) return 0;
+    return sm;
 }
 
 EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active) {
@@ -1128,16 +1265,17 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
     if (sst != CS_OK) return sst;
 
     const int wm = p->nmode == CS_NINV_PIXEL ? 2 : (p->shared_qu ? 0 : 1);
-    const bool shared = p->sched.shared_segments != 0;
+    const int sm = staging_mode(p, mode);
     // the staged kernel's workgroup holds at most 64 KiB of LDS: fewer wavefronts per workgroup
     // when the slices do not fit (same arithmetic, work only regrouped)
     int wpb = p->sched.waves_per_block;
-    const size_t per_wave = wm == 0 ? stage_bytes(mode, shared, p->F) : 0;
+    const size_t per_wave = wm == 0 ? stage_bytes(mode, sm, p->F) : 0;
     while (wpb > 1 && per_wave * (size_t)wpb > 65536) wpb >>= 1;
     a.waves_per_block = wpb;
     int64_t nblocks = (p->nunits + wpb - 1) / wpb;
     if (p->sched.blocks_per_cu > 0) nblocks = std::min<int64_t>(nblocks, (int64_t)p->sched.blocks_per_cu * kNumCu);
     if (nblocks < 1) nblocks = 1;
+    const bool loop = nblocks * wpb < p->nunits;  // persistent grid: wavefronts loop over units
     const dim3 grid((unsigned)nblocks), block((unsigned)(64 * wpb));
     const size_t lds = per_wave * (size_t)wpb;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1154,11 +1292,11 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
         CSI_HIP(hipEventRecord(e0, s));
     }
     if (mode == CS_FP64)
-        launch_pixel_g<double, double>(want_grad, wm, shared, lds, grid, block, s, a);
+        launch_pixel_g<double, double>(want_grad, wm, sm, loop, lds, grid, block, s, a);
     else if (mode == CS_FP32_BULK)
-        launch_pixel_g<float, float>(want_grad, wm, shared, lds, grid, block, s, a);
+        launch_pixel_g<float, float>(want_grad, wm, sm, loop, lds, grid, block, s, a);
     else
-        launch_pixel_g<float, double>(want_grad, wm, shared, lds, grid, block, s, a);
+        launch_pixel_g<float, double>(want_grad, wm, sm, loop, lds, grid, block, s, a);
     CSI_HIP(hipGetLastError());
     if (p->timing) CSI_HIP(hipEventRecord(e1, s));
 

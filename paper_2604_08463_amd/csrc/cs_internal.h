@@ -118,6 +118,7 @@ struct cs_problem {
     std::vector<int64_t> xoff;     // [B+1]
     int64_t kmax_item = 1;         // largest parameter count of one item
     std::vector<int64_t> taboff;   // [B+1] table rows
+    int64_t trows_max = 0;         // largest table row count of one item
     std::vector<int64_t> segoff;   // [B+1] segments of the items (after prepare)
     csi::WsLayout ws;
     char *wsp = nullptr;
@@ -127,7 +128,7 @@ struct cs_problem {
     std::vector<csi::ItemDev> items;
     std::vector<csi::LayoutDev> layouts;
     int64_t nunits = 0;
-    cs_schedule sched{4, 0, 1, 1};
+    cs_schedule sched{2, 0, 1, 2};
     // kernel timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -157,6 +158,8 @@ cs_status export_segments(cs_problem *p, int32_t item, int32_t j, int32_t *perm,
 
 // a2-a7: one batched evaluation (cs_eval.hip)
 EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *active);
+// staging mode that a launch in arithmetic mode `mode` runs under the problem's schedule
+int staging_mode(const cs_problem *p, cs_precision mode);
 cs_status launch_sed(const cs_problem *p, const EvalArgs &a, bool fp32_tables, hipStream_t s);
 cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, double *neg2logl,
                       double *grad, double *cluster_f, int32_t *status, bool want_grad,

@@ -56,7 +56,7 @@ int main() {
     CHECK(cs_optimizer_workspace_bytes(p, 33, &ows) == CS_E_INVALID);
     cs_schedule s{2, 0, 1, 1};
     CHECK(cs_problem_set_schedule(p, &s) == CS_OK);
-    s.shared_segments = 2;
+    s.shared_segments = 3;
     CHECK(cs_problem_set_schedule(p, &s) == CS_E_INVALID);
     cs_schedule g{};
     CHECK(cs_problem_get_schedule(p, &g) == CS_OK && g.shared_segments == 1 && g.waves_per_block == 2);

@@ -143,6 +143,10 @@ def test_schedule_validation(lib):
     rc, h = _create(lib, d)
     s = _lib.Schedule(3, 0, 1)
     assert lib.cs_problem_set_schedule(h, C.byref(s)) == _lib.CS_E_INVALID
+    s = _lib.Schedule(8, 4, 0, 3)  # staging modes are 0, 1 and 2
+    assert lib.cs_problem_set_schedule(h, C.byref(s)) == _lib.CS_E_INVALID
+    s = _lib.Schedule(8, 4, 0, 2)
+    assert lib.cs_problem_set_schedule(h, C.byref(s)) == 0
     s = _lib.Schedule(8, 4, 0)
     assert lib.cs_problem_set_schedule(h, C.byref(s)) == 0
     g = _lib.Schedule()

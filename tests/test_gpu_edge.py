@@ -77,7 +77,7 @@ def test_one_cluster_per_pixel():
     assert len(np.unique(sky.item_labels(0)[0])) == 200
     for precision in ("fp64", "fp32_bulk"):
         prob = cs.Problem.from_sky(sky, precision)
-        for sh in (0, 1):
+        for sh in (0, 1, 2):
             prob.set_schedule(4, 0, 1, sh)
             compare(sky, prob, precision)
 

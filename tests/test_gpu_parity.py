@@ -77,7 +77,7 @@ def test_fp32_bulk_tiny_shapes(nfreq):
     sky = skygen.make_tiny(517, nfreq, (5, 3, 4), seed=100 + nfreq, nitems=3, mask_frac=0.1)
     _log(f"fp32_bulk tiny F={nfreq}")
     prob = cs.Problem.from_sky(sky, "fp32_bulk")
-    for sh in (0, 1):
+    for sh in (0, 1, 2):
         prob.set_schedule(4, 0, 1, sh)
         compare(sky, prob, "fp32_bulk")
 
@@ -123,7 +123,7 @@ def test_fp64_workload2_full():
     _log(f"  worst rel err F {ef:.2e} grad {eg:.2e} cluster {ec:.2e}")
 
 
-@pytest.mark.parametrize("shared", [1, 0])
+@pytest.mark.parametrize("shared", [1, 0, 2])
 @pytest.mark.parametrize("precision", ["fp32_bulk", "fp32_store", "fp64"])
 def test_precisions_and_sharing_workload2(precision, shared):
     sky = skygen.make_config(2, nitems=4)
@@ -140,7 +140,7 @@ def test_segment_sharing_ragged_many_segments(precision):
     # counts, and chunks past the staging limit)
     sky = skygen.make_config(4, nitems=3, kmax4=(3000, 500, 1000))
     prob = cs.Problem.from_sky(sky, precision)
-    for sh in (1, 0):
+    for sh in (1, 0, 2):
         prob.set_schedule(4, 0, 1, sh)
         compare(sky, prob, precision)
 
@@ -214,8 +214,9 @@ def test_batched_equals_per_item_and_schedules_bit_identical():
         assert f1.item() == f[b]
         assert np.array_equal(g1.cpu().numpy(), g[off[b]:off[b + 1]])
     # schedules move work between wavefronts only: bit-identical within one arithmetic mode;
-    # the per-pixel and segment-shared modes differ by rounding order only
-    for sh in (1, 0):
+    # the staging modes differ by rounding order only (the segment-sum mode runs as the
+    # per-pixel mode with FP64 accumulation)
+    for sh in (1, 0, 2):
         ref = None
         for wpb in (1, 2, 8):
             for bpc in (0, 2):
@@ -229,7 +230,7 @@ def test_batched_equals_per_item_and_schedules_bit_identical():
                     assert np.array_equal(f2, ref[0]) and np.array_equal(g2, ref[1])
 
 
-@pytest.mark.parametrize("shared", [1, 0])
+@pytest.mark.parametrize("shared", [1, 0, 2])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk", "fp32_store"])
 def test_likelihood_without_gradient_matches(precision, shared):
     # the F-only kernels accumulate M and b as the gradient kernels do
@@ -440,15 +441,21 @@ def test_workload5_full_size_sampled_items():
     for precision, tf in (("fp32_bulk", 1e-5), ("fp64", 1e-12)):
         prob = cs.Problem.from_sky(sky, precision)
         s = prob.autotune(x, reps=1)
-        f, g, _, st = gpu_eval(prob, sky, cluster=False)
-        for b in picks:
-            fo, go, _, so = ref[b]
-            ef = abs(f[b] - fo) / abs(fo)
-            _log(f"workload 5 {precision} schedule ({s.waves_per_block},{s.blocks_per_cu},{s.xcd_remap},"
-                 f"{s.shared_segments}) item {b}: rel F {ef:.2e}")
-            assert st[b] == so and ef <= tf
-            eg, r = check_grad(precision, sky.nfreq, g[off[b]:off[b + 1]], go, terms[b])
-            _log(f"  gradient normwise {eg:.2e}, worst ratio to the FP32 bound {r:.3f}")
-        assert np.all(np.isfinite(f)) and np.all(st == 0)
+        # the autotuned schedule, then each staging mode by hand (FP32: per-pixel and segment sums)
+        scheds = [None] + ([(2, 0, 0, 0), (2, 0, 0, 2)] if precision == "fp32_bulk" else [])
+        for sc in scheds:
+            if sc is not None:
+                prob.set_schedule(*sc)
+                s = prob.get_schedule()
+            f, g, _, st = gpu_eval(prob, sky, cluster=False)
+            for b in picks:
+                fo, go, _, so = ref[b]
+                ef = abs(f[b] - fo) / abs(fo)
+                _log(f"workload 5 {precision} schedule ({s.waves_per_block},{s.blocks_per_cu},{s.xcd_remap},"
+                     f"{s.shared_segments}) item {b}: rel F {ef:.2e}")
+                assert st[b] == so and ef <= tf
+                eg, r = check_grad(precision, sky.nfreq, g[off[b]:off[b + 1]], go, terms[b])
+                _log(f"  gradient normwise {eg:.2e}, worst ratio to the FP32 bound {r:.3f}")
+            assert np.all(np.isfinite(f)) and np.all(st == 0)
         del prob
         torch.cuda.empty_cache()

@@ -78,7 +78,6 @@ static void carve(cs_problem *p) {
     w.partials = take(sizeof(double) * 4 * w.p64 * B);
     w.segoff = take(sizeof(int64_t) * (B + 1));
     w.istatus = take(sizeof(int32_t) * B);
-    w.fpart = take(sizeof(double) * 2 * kFSlices * B);
     w.total = off;
 }
 

@@ -6,9 +6,8 @@
 //                  and the adjoint sums (a4), FP64 3x3 Cholesky (a5), per-pixel gradient (a6),
 //                  run-segmented wave reduction (a7, first level); k_pixel is the direct-gather
 //                  form for per-Stokes or per-pixel weights
-//   k_fin_grad     per (item, cluster): compensated sum over the cluster's segments, and F of
-//                  each item in slices of its segments (a7)
-//   k_fin_f        per item: the slices of F folded in order, and the status word (a7)
+//   k_fin_grad     per (item, cluster): compensated sum over the cluster's segments; per item:
+//                  F over all its segments and the status word (a7)
 //
 // Gradient without a second pass over the data.  With r_s = N^-1 (d_s - A s_hat_s) and
 // delta_k(nu) = dA/dtheta_k (only one column depends on theta_k),
@@ -218,9 +217,12 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
 
 // a7 (first level): inclusive scan inside each constant-label run of the wavefront; the run's
 // last lane holds the run total and writes the segment's (f, dF/dbeta_d, dF/dT_d, dF/dbeta_s).
+// Run-segmented sums of the wavefront's per-pixel values; the last lane of each segment writes
+// the segment's (f, dF/dbeta_d, dF/dT_d, dF/dbeta_s).  A non-finite gradient partial sets the
+// item's NONFINITE bit here (every lane of the wavefront must be active).
 template <bool GRAD>
 __device__ __forceinline__ void seg_reduce_write(uint64_t head, int lane, double fpix, double g1, double g2,
-                                                 double g3, double *out) {
+                                                 double g3, double *out, int32_t *status) {
     const int start = 63 - __clzll(head & lanemask_le(lane));
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -247,6 +249,8 @@ __device__ __forceinline__ void seg_reduce_write(uint64_t head, int lane, double
         out[2] = GRAD ? g2 : 0.0;
         out[3] = GRAD ? g3 : 0.0;
     }
+    if (GRAD && __ballot(last && !(isfinite(g1) && isfinite(g2) && isfinite(g3))) && lane == 0)
+        atomicOr(status, (int)CS_ITEM_NONFINITE);
 }
 
 // WM: 0 = band weights shared by Q and U, 1 = band weights per Stokes, 2 = per-pixel weights.
@@ -396,7 +400,8 @@ __device__ __forceinline__ void unit_pixel(const EvalArgs &a, const int item, co
         const uint64_t bad = __ballot(valid && !ok);
         if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
 
-        seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (part_off + segbase + segl) * 4);
+        seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (part_off + segbase + segl) * 4,
+                               &a.istatus[item]);
     }
 }
 
@@ -942,7 +947,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     }
     const uint64_t bad = __ballot(valid && !ok);
     if (bad && lane == 0) atomicOr(&a.istatus[item], (int)CS_ITEM_NOT_PD);
-    seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (it->part_off + segbase + segl) * 4);
+    seg_reduce_write<GRAD>(head, lane, fpix, g1, g2, g3, a.partials + (it->part_off + segbase + segl) * 4,
+                           &a.istatus[item]);
     // the slice is rewritten by the wavefront's next unit
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -996,14 +1002,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
 // ---------------------------------------------------------------------------------------------
 // a7 (second level): deterministic compensated sums over each cluster's segments
 // ---------------------------------------------------------------------------------------------
-// One launch for the second level of a7.  Its first nitems * kFSlices workgroups each add one
-// slice of an item's segment values f (Neumaier, then a fixed tree over the workgroup) into
-// fpart; k_fin_f folds the slices in order.  The remaining workgroups hold kFinLanes lanes per
-// (item, cluster): lane l of a cluster's group adds the cluster's segments l, l + kFinLanes, ...
-// in order, and the group's lane sums are combined by a fixed butterfly, so no result depends on
-// timing.  Workgroups are dealt round-robin to the XCDs, so the cluster part of the grid is
-// renumbered in groups of eight items: the blocks of one item all land on one XCD, whose L2 then
-// holds its partials.
+// One launch for the second level of a7.  Its first nitems workgroups each add all of one item's
+// segment values f (Neumaier per thread over a fixed stride, then a fixed tree over the
+// workgroup) and write F and the item's status word: NOT_PD and NONFINITE were set by the pixel
+// kernel (a non-positive-definite pixel, a non-finite gradient partial), and F non-finite adds
+// NONFINITE.  The remaining workgroups hold kFinLanes lanes per (item, cluster): lane l of a
+// cluster's group adds the cluster's segments l, l + kFinLanes, ... in order, and the group's
+// lane sums are combined by a fixed butterfly, so no result depends on timing.  (A cluster sum
+// of finite partials that overflows is not flagged.)  Workgroups are dealt round-robin to the
+// XCDs, so the cluster part of the grid is renumbered in groups of eight items: the blocks of one
+// item all land on one XCD, whose L2 then holds its partials.
 constexpr int kFinLanes = 4;
 constexpr int kFinBlock = 256;
 
@@ -1013,20 +1021,19 @@ __device__ __forceinline__ void neu_combine(double &s, double &c, int off) {
     c += co;
 }
 
-__device__ __forceinline__ void f_slice(const EvalArgs &a, const int item, const int sl) {
+__device__ __forceinline__ void f_item(const EvalArgs &a, const int item, double *neg2logl, int32_t *status) {
     const ItemDev &it = a.items[item];
     const LayoutDev &L = a.layouts[it.layout];
     const int64_t n = L.nseg;
-    const int64_t b = sl * n / kFSlices, e = (sl + 1) * n / kFSlices;
     const double *part = a.partials + it.part_off * 4;
     double s = 0, c = 0;
-    constexpr int kU = 4;
-    for (int64_t i0 = b + threadIdx.x; i0 < e; i0 += kU * kFinBlock) {
+    constexpr int kU = 8;  // loads in flight per thread
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += kU * kFinBlock) {
         double v[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             const int64_t i = i0 + (int64_t)k * kFinBlock;
-            v[k] = i < e ? part[i * 4] : 0.0;
+            v[k] = i < n ? part[i * 4] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) neu_add(s, c, v[k]);
@@ -1045,24 +1052,30 @@ __device__ __forceinline__ void f_slice(const EvalArgs &a, const int item, const
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double *o = a.fpart + ((int64_t)item * kFSlices + sl) * 2;
-        o[0] = ss[0];
-        o[1] = sc[0];
+        int st = a.istatus[item];
+        double v = ss[0] + sc[0];
+        if (st & CS_ITEM_NOT_PD)
+            v = __builtin_nan("");
+        else if (!isfinite(v))
+            st |= CS_ITEM_NONFINITE;
+        neg2logl[item] = v;
+        if (status) status[item] = st;
+        a.istatus[item] = st;
     }
 }
 
 template <bool WG, bool WF>
 __global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, int nitems,
-                                                        int kblocks, double *grad, double *cluster_f) {
-    const int64_t nf = (int64_t)nitems * kFSlices;
-    if ((int64_t)blockIdx.x < nf) {  // F slices
-        const int item = item0 + (int)(blockIdx.x / kFSlices);
+                                                        int kblocks, double *grad, double *cluster_f,
+                                                        double *neg2logl, int32_t *status) {
+    if ((int)blockIdx.x < nitems) {  // F and status of one item
+        const int item = item0 + (int)blockIdx.x;
         if (a.active && !as_const(a.active)[item]) return;
-        f_slice(a, item, (int)(blockIdx.x % kFSlices));
+        f_item(a, item, neg2logl, status);
         return;
     }
     if (!WG && !WF) return;
-    const int64_t lin = blockIdx.x - nf;
+    const int64_t lin = blockIdx.x - nitems;
     const int64_t grp = lin / (kNumXcd * (int64_t)kblocks);
     const int64_t rem = lin - grp * kNumXcd * (int64_t)kblocks;
     const int ng = (int)min((int64_t)kNumXcd, (int64_t)nitems - grp * kNumXcd);  // items in this group
@@ -1124,36 +1137,8 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, const 
         if (WF) neu_combine(fs, fc, off);
     }
     if (sub != 0) return;
-    if (WG) {
-        const double v = gs + gc;
-        grad[g] = v;
-        if (!isfinite(v)) atomicOr(&a.istatus[item], (int)CS_ITEM_NONFINITE);
-    }
+    if (WG) grad[g] = gs + gc;
     if (WF) cluster_f[g] = fs + fc;
-}
-
-// F of each item: its slices folded in order, then the status word (after the cluster sums,
-// which flag a non-finite gradient).  One thread per item.
-__global__ __launch_bounds__(256) void k_fin_f(const EvalArgs a, double *neg2logl, int32_t *status) {
-    const int item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= a.nitems) return;
-    if (a.active && !a.active[item]) return;
-    const double *fp = a.fpart + (int64_t)item * kFSlices * 2;
-    double s = 0, c = 0;
-#pragma unroll
-    for (int sl = 0; sl < kFSlices; ++sl) {
-        neu_add(s, c, fp[2 * sl]);
-        c += fp[2 * sl + 1];
-    }
-    int st = a.istatus[item];
-    double v = s + c;
-    if (st & CS_ITEM_NOT_PD)
-        v = __builtin_nan("");
-    else if (!isfinite(v))
-        st |= CS_ITEM_NONFINITE;
-    neg2logl[item] = v;
-    if (status) status[item] = st;
-    a.istatus[item] = st;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1227,7 +1212,6 @@ EvalArgs make_eval_args(const cs_problem *p, const double *x, const int32_t *act
     a.band = (const BandDev *)(p->wsp + w.band);
     a.partials = (double *)(p->wsp + w.partials);
     a.istatus = (int32_t *)(p->wsp + w.istatus);
-    a.fpart = (double *)(p->wsp + w.fpart);
     a.active = active;
     a.x = x;
     a.nitems = p->B;
@@ -1302,7 +1286,7 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
 
     {
         // items per launch: the 1D grid stays below 2^31 workgroups
-        const int64_t per_item = (int64_t)kFSlices + ((want_grad || cluster_f) ? (int64_t)kblocks : 0);
+        const int64_t per_item = 1 + ((want_grad || cluster_f) ? (int64_t)kblocks : 0);
         const int per = (int)std::min<int64_t>(p->B, std::max<int64_t>(1, ((int64_t(1) << 31) - 1) / per_item));
         for (int b0 = 0; b0 < p->B; b0 += per) {
             const int nb = std::min(per, p->B - b0);
@@ -1310,21 +1294,19 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
             const int kb = (int)kblocks;
             if (want_grad && cluster_f)
                 hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
-                                   cluster_f);
+                                   cluster_f, neg2logl, status);
             else if (want_grad)
                 hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
-                                   cluster_f);
+                                   cluster_f, neg2logl, status);
             else if (cluster_f)
                 hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
-                                   cluster_f);
+                                   cluster_f, neg2logl, status);
             else
                 hipLaunchKernelGGL((k_fin_grad<false, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
-                                   cluster_f);
+                                   cluster_f, neg2logl, status);
             CSI_HIP(hipGetLastError());
         }
     }
-    hipLaunchKernelGGL(k_fin_f, dim3((unsigned)((p->B + 255) / 256)), dim3(256), 0, s, a, neg2logl, status);
-    CSI_HIP(hipGetLastError());
     return CS_OK;
 }
 

@@ -14,7 +14,6 @@ namespace csi {
 
 constexpr int kChunk = 64;  // pixels per work unit = lanes of one wavefront
 constexpr int kFMax = 32;   // largest supported band count (register tile)
-constexpr int kFSlices = 8;     // slices of an item's segments summed by separate workgroups for F
 constexpr int kSegLabPad = 16;  // records past the end of each seg_lab array (read, never used)
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int kNumCu = 256;
@@ -77,7 +76,6 @@ struct EvalArgs {
     const BandDev *band;
     double *partials;    // [segment][4]: f, dF/dbeta_d, dF/dT_d, dF/dbeta_s
     int32_t *istatus;    // [B] status bits of the current evaluation
-    double *fpart;       // [B][kFSlices][2]: compensated partial sums of F per slice of segments
     const int32_t *active;  // nullable [B]: 0 = skip item (converged optimiser items)
     const double *x;     // packed parameters
     int32_t nitems;
@@ -89,7 +87,7 @@ struct EvalArgs {
 // Workspace regions (byte offsets, 256-aligned), see carve_workspace().
 struct WsLayout {
     size_t band, items, layouts, units, keys, order, head, seg_base, seg_lab, seg_perm, seg_off,
-        counts, excl, dpack, wpack, tables, partials, segoff, istatus, fpart, total;
+        counts, excl, dpack, wpack, tables, partials, segoff, istatus, total;
     size_t keys_stride, p64, nchunk_max, np2, kmax[3];
 };
 

@@ -496,6 +496,7 @@ def main():
     abytes = algorithmic_bytes(p32, sky, 4)
     kavg = kms / max(nl, 1)
     achieved = abytes / (kavg * 1e-3) / 1e9
+    traffic = measured_traffic(sched)  # HBM bytes per launch from the committed counter record, or None
     log(f"fp32_bulk: {value:.1f} evals/s, {ms_per_step:.3f} ms/step, pixel kernel {kavg:.3f} ms, "
         f"{achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of peak, {achieved / copy_gbs:.1%} of the copy)")
     del p32
@@ -566,11 +567,13 @@ def main():
                    "npix": sky.npix, "nfreq": sky.nfreq, "items": sky.nitems,
                    "clusters": sky.nclusters[0].tolist(), "schedule": sched},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_pixel_stage (fused likelihood + adjoint, schedule mode "
                                f"{sched.get('shared_segments') if sched else 'default'})",
                      "kernel_ms": kavg, "bytes_per_launch": abytes, "copy_gbs": copy_gbs,
-                     "frac_of_copy": achieved / copy_gbs},
+                     "frac_of_copy": achieved / copy_gbs,
+                     # counted HBM traffic (fetch + write) over the same launch duration
+                     "traffic_gbs": traffic / (kavg * 1e-3) / 1e9 if traffic else None},
         "cpu_baseline": cpu,
         "fp64_path": fp64,
         "fp32_vs_fp64": err,

@@ -1014,6 +1014,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves
 // item all land on one XCD, whose L2 then holds its partials.
 constexpr int kFinLanes = 4;
 constexpr int kFinBlock = 256;
+__constant__ int32_t kAllActive = 1;  // read in place of the active flags when the caller passes none
 
 __device__ __forceinline__ void neu_combine(double &s, double &c, int off) {
     const double so = __shfl_xor(s, off, kFinLanes), co = __shfl_xor(c, off, kFinLanes);
@@ -1065,7 +1066,7 @@ __device__ __forceinline__ void f_item(const EvalArgs &a, const int item, double
 }
 
 template <bool WG, bool WF>
-__global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, const int64_t *xoff, int item0, int nitems,
+__global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, int item0, int nitems,
                                                         int kblocks, double *grad, double *cluster_f,
                                                         double *neg2logl, int32_t *status) {
     if ((int)blockIdx.x < nitems) {  // F and status of one item
@@ -1081,26 +1082,45 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_grad(const EvalArgs a, const 
     const int ng = (int)min((int64_t)kNumXcd, (int64_t)nitems - grp * kNumXcd);  // items in this group
     const int item = item0 + (int)(grp * kNumXcd + rem % ng);
     const int64_t xb = rem / ng;
-    if (a.active && !as_const(a.active)[item]) return;
-    const int64_t x0 = as_const(xoff)[item];
+    // The descriptors come through the scalar cache in two batches: the kernel arguments, then the
+    // item's record, its active flag and the first layout's CSR pointers (the layout of every item
+    // when the labels are shared); an item with a layout of its own reads that layout after them.
+    asm volatile("" ::"s"(a.items), "s"(a.layouts), "s"(a.active), "s"(a.partials), "s"(grad), "s"(cluster_f));
+    const cptr<ItemDev> it = as_const(a.items) + item;
+    const cptr<int32_t> actp = a.active ? as_const(a.active) + item : as_const(&kAllActive);
+    const int32_t lay = it->layout, act = *actp;
+    const int64_t k0 = it->k[0], k1 = it->k[1], k2 = it->k[2], x0 = it->xoff, poff = it->part_off;
+    cptr<LayoutDev> L = as_const(a.layouts);
+    const int32_t *perm0 = L->seg_perm[0], *perm1 = L->seg_perm[1], *perm2 = L->seg_perm[2];
+    const int32_t *off0 = L->seg_off[0], *off1 = L->seg_off[1], *off2 = L->seg_off[2];
+    asm volatile("" ::"s"(lay), "s"(act), "s"(k0), "s"(k1), "s"(k2), "s"(x0), "s"(poff), "s"(perm0), "s"(perm1),
+                 "s"(perm2), "s"(off0), "s"(off1), "s"(off2));
+    if (!act) return;
     const int sub = threadIdx.x % kFinLanes;
     int64_t r = xb * (kFinBlock / kFinLanes) + threadIdx.x / kFinLanes;
-    if (r >= as_const(xoff)[item + 1] - x0) return;  // whole groups leave together
+    if (r >= k0 + k1 + k2) return;  // whole groups leave together
     const int64_t g = x0 + r;
-    const ItemDev &it = a.items[item];
-    const LayoutDev &L = a.layouts[it.layout];
+    if (lay != 0) {
+        L = as_const(a.layouts) + lay;
+        perm0 = L->seg_perm[0], perm1 = L->seg_perm[1], perm2 = L->seg_perm[2];
+        off0 = L->seg_off[0], off1 = L->seg_off[1], off2 = L->seg_off[2];
+    }
     int j = 0;
-    if (r >= it.k[0]) {
-        r -= it.k[0];
+    const int32_t *perm = perm0, *soff = off0;
+    if (r >= k0) {
+        r -= k0;
         j = 1;
-        if (r >= it.k[1]) {
-            r -= it.k[1];
+        perm = perm1;
+        soff = off1;
+        if (r >= k1) {
+            r -= k1;
             j = 2;
+            perm = perm2;
+            soff = off2;
         }
     }
-    const int32_t *perm = L.seg_perm[j];
-    const int b = L.seg_off[j][r], e = L.seg_off[j][r + 1];
-    const double *part = a.partials + it.part_off * 4;
+    const int b = soff[r], e = soff[r + 1];
+    const double *part = a.partials + poff * 4;
     double gs = 0, gc = 0, fs = 0, fc = 0;
     // segments are scattered in the partials: kB of the lane's segments are requested at a time,
     // with the next batch's segment indices already in flight
@@ -1241,7 +1261,6 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
                       double *cluster_f, int32_t *status, bool want_grad, cs_precision mode, hipStream_t s) {
     const WsLayout &w = p->ws;
     EvalArgs a = make_eval_args(p, x, active);
-    const int64_t *xoff_dev = (const int64_t *)(p->wsp + w.items + sizeof(ItemDev) * (size_t)p->B);
     const bool t32 = (mode == CS_FP32_BULK);
     const unsigned kblocks = (unsigned)((p->kmax_item * kFinLanes + kFinBlock - 1) / kFinBlock);
 
@@ -1293,16 +1312,16 @@ cs_status launch_eval(cs_problem *p, const double *x, const int32_t *active, dou
             const dim3 fgrid((unsigned)(per_item * nb));
             const int kb = (int)kblocks;
             if (want_grad && cluster_f)
-                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<true, true>), fgrid, dim3(kFinBlock), 0, s, a, b0, nb, kb, grad,
                                    cluster_f, neg2logl, status);
             else if (want_grad)
-                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<true, false>), fgrid, dim3(kFinBlock), 0, s, a, b0, nb, kb, grad,
                                    cluster_f, neg2logl, status);
             else if (cluster_f)
-                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<false, true>), fgrid, dim3(kFinBlock), 0, s, a, b0, nb, kb, grad,
                                    cluster_f, neg2logl, status);
             else
-                hipLaunchKernelGGL((k_fin_grad<false, false>), fgrid, dim3(kFinBlock), 0, s, a, xoff_dev, b0, nb, kb, grad,
+                hipLaunchKernelGGL((k_fin_grad<false, false>), fgrid, dim3(kFinBlock), 0, s, a, b0, nb, kb, grad,
                                    cluster_f, neg2logl, status);
             CSI_HIP(hipGetLastError());
         }

@@ -16,7 +16,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "cs_internal.h"
+#include "cs_device.h"
 
 namespace csi {
 
@@ -52,22 +52,66 @@ struct OptArgs {
     double lr, b1, b2, eps, topk;
 };
 
+// An item's state record read through the scalar cache: it is the same for every thread of the
+// item's workgroup, so it stays in scalar registers.
+__device__ __forceinline__ OptItem load_uniform(const OptItem *p) {
+    constexpr int kW = sizeof(OptItem) / 4;
+    const cptr<uint32_t> q = (cptr<uint32_t>)as_const(p);
+    uint32_t w[kW];
+#pragma unroll
+    for (int i = 0; i < kW; ++i) w[i] = q[i];
+    OptItem s;
+    __builtin_memcpy(&s, w, sizeof s);
+    return s;
+}
+
 constexpr int kOptThreads = 256;   // block size of the small per-item kernels
 constexpr int32_t kSwitch = 1 << 8;  // internal status bit: the item reached the FP32 phase's tolerance
 constexpr double kFlatRel = 1e-12;  // relative change of F below which Armijo is not resolved
 
-// deterministic block sum of N values (fixed shuffle tree, then the waves in order)
+// Wave-level sums and maxima by DPP lane moves (VALU only, no LDS round trip): swap neighbouring
+// lanes, then the lane pairs of each quad, mirror each half-row, mirror each row, so every lane
+// of a 16-lane row holds that row's result; the four row results are then read in row order.
+// Each step combines two lanes' values symmetrically, so the lanes of a row agree bit for bit and
+// the result is independent of timing.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+constexpr int kDppSwap1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppSwap2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror
+constexpr int kDppMirror = 0x140;      // row_mirror
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_f64<kDppSwap1>(x);
+    x += dpp_f64<kDppSwap2>(x);
+    x += dpp_f64<kDppHalfMirror>(x);
+    x += dpp_f64<kDppMirror>(x);
+    return ((lane_f64(x, 0) + lane_f64(x, 16)) + lane_f64(x, 32)) + lane_f64(x, 48);
+}
+__device__ __forceinline__ double wave_max(double x) {
+    x = fmax(x, dpp_f64<kDppSwap1>(x));
+    x = fmax(x, dpp_f64<kDppSwap2>(x));
+    x = fmax(x, dpp_f64<kDppHalfMirror>(x));
+    x = fmax(x, dpp_f64<kDppMirror>(x));
+    return fmax(fmax(fmax(lane_f64(x, 0), lane_f64(x, 16)), lane_f64(x, 32)), lane_f64(x, 48));
+}
+
+// deterministic block sum of N values (the wave sums above, then the waves in order)
 template <int N, int NT>
 __device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[16]) {
     constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        double x = v[n];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        v[n] = x;
-        if (NWV > 1 && lane == 0) sh[n][wave] = x;
+        v[n] = wave_sum(v[n]);
+        if (NWV > 1 && lane == 0) sh[n][wave] = v[n];
     }
     if (NWV > 1) {
         __syncthreads();
@@ -76,7 +120,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[16]) {
             double x = 0;
 #pragma unroll
             for (int w = 0; w < NWV; ++w) x += sh[n][w];
-            v[n] = x;
+            v[n] = lane_f64(x, 0);  // the same in every lane; held in scalar registers from here
         }
         __syncthreads();
     }
@@ -86,8 +130,7 @@ template <int NT>
 __device__ __forceinline__ double block_max(double v, double *sh) {
     constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    v = wave_max(v);
     if (NWV == 1) return v;
     if (lane == 0) sh[wave] = v;
     __syncthreads();
@@ -95,7 +138,7 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 #pragma unroll
     for (int w = 1; w < NWV; ++w) x = fmax(x, sh[w]);
     __syncthreads();
-    return x;
+    return lane_f64(x, 0);
 }
 
 // Stopping tests after an accepted step, in order: the relative projected-gradient tolerance,
@@ -147,17 +190,17 @@ __global__ __launch_bounds__(kOptThreads) void k_opt_init(OptArgs a, const doubl
 template <int NT>
 __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
     const int item = blockIdx.x;
-    if (!a.active[item]) return;
+    if (!as_const(a.active)[item]) return;
     __shared__ double red[8][16];
     __shared__ double rho[32], alp[32];
     const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
     const int tid = threadIdx.x;
     const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
     double *y = a.y + o, *g = a.g + o, *p = a.p + o, *yt = a.yt + o, *xt = a.xt + o;
-    OptItem s = a.st[item];  // every thread holds the same copy
+    OptItem s = load_uniform(a.st + item);  // every thread holds the same copy, in scalar registers
     s.nevals += 1;
-    const double fe = a.fe[item];
-    const int32_t est = a.estat[item];
+    const double fe = as_const(a.fe)[item];
+    const int32_t est = as_const(a.estat)[item];
     const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
     int32_t finish = 0;
     bool need_dir = false;
@@ -392,40 +435,37 @@ __global__ __launch_bounds__(NT) void k_opt_update(OptArgs a) {
     }
 }
 
-// The same step with the item's vectors held in registers: thread t owns elements k NT + t,
-// k < PT (K <= NT PT), so every load instruction of a wavefront is one contiguous span.  The free
-// mask and the direction stay in registers for the whole step; each two-loop pass streams only
-// its pair (s_j, t_j), requested during the previous pass's block reduction, and keeps the vector
-// the next pass's pending update needs.  Each thread's partial sums run over its elements in
-// order, as in k_opt_update; the workgroup size (and so the reduction tree) may differ.
+// The same step with the work spread over a workgroup's registers: thread t owns elements k NT + t,
+// k < PT (K <= NT PT), so every load instruction of a wavefront is one contiguous span.  y and g
+// live in memory (the item's vectors stay in L2 between the phases): each phase reads what it
+// needs, and y and g are written back as soon as they change, so only the direction (and the
+// two-loop buffers) occupy registers across phases.  Each two-loop pass streams only its pair
+// (s_j, t_j), requested during the previous pass's block reduction, and keeps the vector the next
+// pass's pending update needs.  Each thread's partial sums run over its elements in order, as in
+// k_opt_update; the workgroup size (and so the reduction tree) may differ.
 template <int NT, int PT>
 __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
     const int item = blockIdx.x;
-    if (!a.active[item]) return;
+    if (!as_const(a.active)[item]) return;
     __shared__ double red[8][16];
     __shared__ double rho[32], alp[32];
-    const int64_t o = a.xoff[item], K = a.xoff[item + 1] - o;
+    const int64_t o = as_const(a.xoff)[item], K = as_const(a.xoff)[item + 1] - o;
     const int tid = threadIdx.x;
     const double *lo = a.lo + o, *hi = a.hi + o, *ge = a.ge + o;
     double *yg = a.y + o, *gg = a.g + o, *pgl = a.p + o, *ytg = a.yt + o, *xtg = a.xt + o;
-    OptItem s = a.st[item];  // every thread holds the same copy
+    OptItem s = load_uniform(a.st + item);  // every thread holds the same copy, in scalar registers
     s.nevals += 1;
-    const double fe = a.fe[item];
-    const int32_t est = a.estat[item];
+    const double fe = as_const(a.fe)[item];
+    const int32_t est = as_const(a.estat)[item];
     const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
     int32_t finish = 0;
     bool need_dir = false;
-
-    // y, g and the direction (which also holds the two-loop vector) of the thread's elements
-    double y[PT], g[PT], pv[PT];
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const int64_t i = (int64_t)k * NT + tid;
-        const bool in = i < K;
-        y[k] = in ? yg[i] : 0.0;
-        g[k] = in ? gg[i] : 0.0;
-        pv[k] = in ? pgl[i] : 0.0;
-    }
+    auto in = [&](int k) { return tid < K - (int64_t)k * NT; };
+    auto at = [&](auto *v, int k) { return v + (int64_t)k * NT + tid; };  // element k of the thread
+    // gradient at the trial in the box coordinates
+    auto gtrial = [&](int k) { return *at(ge, k) * (*at(hi, k) - *at(lo, k)); };
+    // phases re-read y and g from memory rather than holding them in registers
+    auto phase_break = [] { asm volatile("" ::: "memory"); };
 
     if (s.state == ST_INIT || s.state == ST_REINIT) {
         if (!evalok) {
@@ -434,13 +474,12 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
         } else {
             double v[1] = {0.0};
 #pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
-                if (i < K) {
-                    g[k] = ge[i] * (hi[i] - lo[i]);
-                    if (is_free(y[k], g[k])) v[0] += g[k] * g[k];
+            for (int k = 0; k < PT; ++k)
+                if (in(k)) {
+                    const double gk = gtrial(k);
+                    *at(gg, k) = gk;
+                    if (is_free(*at(yg, k), gk)) v[0] += gk * gk;
                 }
-            }
             block_sum<1, NT>(v, red);
             s.f = fe;
             if (s.state == ST_INIT) {
@@ -457,16 +496,14 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (evalok) {
 #pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
-                if (i < K) {
-                    const double si = ytg[i] - y[k], gti = ge[i] * (hi[i] - lo[i]), ti = gti - g[k];
+            for (int k = 0; k < PT; ++k)
+                if (in(k)) {
+                    const double si = *at(ytg, k) - *at(yg, k), gti = gtrial(k), ti = gti - *at(gg, k);
                     v[0] += si * ti;
                     v[1] += si * si;
                     v[2] += ti * ti;
                     v[3] += gti * si;
                 }
-            }
         }
         block_sum<4, NT>(v, red);
         const bool flat = fabs(fe - s.f) <= kFlatRel * fabs(s.f) && v[3] <= 0.0;
@@ -475,20 +512,19 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             const int nw = keep ? (s.newest + 1) % a.m : s.newest;
             double *Sn = a.S + (int64_t)nw * a.ktot + o, *Tn = a.T + (int64_t)nw * a.ktot + o;
             double pg[1] = {0.0};
+            phase_break();
 #pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
-                if (i < K) {
-                    const double yti = ytg[i], gti = ge[i] * (hi[i] - lo[i]);
+            for (int k = 0; k < PT; ++k)
+                if (in(k)) {
+                    const double yti = *at(ytg, k), gti = gtrial(k);
                     if (keep) {
-                        Sn[i] = yti - y[k];
-                        Tn[i] = gti - g[k];
+                        *at(Sn, k) = yti - *at(yg, k);
+                        *at(Tn, k) = gti - *at(gg, k);
                     }
-                    y[k] = yti;
-                    g[k] = gti;
-                    if (is_free(y[k], g[k])) pg[0] += g[k] * g[k];
+                    *at(yg, k) = yti;
+                    *at(gg, k) = gti;
+                    if (is_free(yti, gti)) pg[0] += gti * gti;
                 }
-            }
             block_sum<1, NT>(pg, red);
             if (keep) {
                 s.newest = nw;
@@ -506,26 +542,25 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
                 s.alpha *= 0.5;
         }
     }
+    phase_break();
 
+    double pv[PT];  // the direction, also the two-loop vector
+    bool pv_new = need_dir;  // the direction differs from the stored one
     if (need_dir) {
         // two-loop recursion on the free set, q (in pv) = P g; carry = t (backward) or s (forward)
         // of the last used pair, whose update is applied at the start of the next pass.  Each
         // pass requests the next pair (s_j, t_j) before its block reduction, so the history stream
-        // overlaps the reductions; y and g are parked in memory meanwhile, and the oldest pair,
-        // last of the backward pass, is the forward pass's first.
+        // overlaps the reductions; the oldest pair, last of the backward pass, is the forward
+        // pass's first.
         unsigned fr = 0;
         double carry[PT];
 #pragma unroll
         for (int k = 0; k < PT; ++k) {
-            const int64_t i = (int64_t)k * NT + tid;
-            const bool f = (i < K) && is_free(y[k], g[k]);
+            const double gk = in(k) ? *at(gg, k) : 0.0;
+            const bool f = in(k) && is_free(*at(yg, k), gk);
             fr |= (unsigned)f << k;
-            pv[k] = f ? g[k] : 0.0;
+            pv[k] = f ? gk : 0.0;
             carry[k] = 0.0;
-            if (i < K) {
-                yg[i] = y[k];
-                gg[i] = g[k];
-            }
         }
         const int np = s.npairs, m = a.m;
         auto pair_at = [&](int c) { return ((s.newest - c) % m + m) % m; };
@@ -534,10 +569,10 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             const double *Sj = a.S + (int64_t)j * a.ktot + o, *Tj = a.T + (int64_t)j * a.ktot + o;
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
+                const int64_t kb = (int64_t)k * NT;
                 const bool f = (fr >> k) & 1u;
-                sn[k] = f ? Sj[i] : 0.0;
-                tn[k] = f ? Tj[i] : 0.0;
+                sn[k] = f ? (Sj + kb)[tid] : 0.0;
+                tn[k] = f ? (Tj + kb)[tid] : 0.0;
             }
         };
         if (np > 0) fetch(pair_at(0));
@@ -551,15 +586,14 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const bool f = (fr >> k) & 1u;
-                if (pend && f) pv[k] -= penda * carry[k];
+                // no free-set test: s, t and q are zero outside the free set, so those elements
+                // add exact zeros
+                if (pend) pv[k] -= penda * carry[k];
                 const double si = sn[k], ti = tn[k];
-                if (f) {
-                    v[0] += si * ti;
-                    v[1] += si * si;
-                    v[2] += ti * ti;
-                    v[3] += si * pv[k];
-                }
+                v[0] += si * ti;
+                v[1] += si * si;
+                v[2] += ti * ti;
+                v[3] += si * pv[k];
                 carry[k] = ti;
             }
             if (c + 1 < np) fetch(pair_at(c + 1));  // the oldest pair stays in sn, tn
@@ -604,10 +638,9 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             double v[1] = {0.0};
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const bool f = (fr >> k) & 1u;
-                if (spend && f) pv[k] += carry[k] * pendc;
+                if (spend) pv[k] += carry[k] * pendc;
                 const double si = sn[k];
-                if (f) v[0] += tn[k] * pv[k];
+                v[0] += tn[k] * pv[k];
                 carry[k] = si;
             }
             const int cn = next_used(c - 1);
@@ -617,15 +650,8 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             pendc = alp[j] - rj * v[0];
             c = cn;
         }
-        // y and g back from memory (the recursion did not hold them)
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            const int64_t i = (int64_t)k * NT + tid;
-            y[k] = i < K ? yg[i] : 0.0;
-            g[k] = i < K ? gg[i] : 0.0;
-        }
         // p = -(H P g) on the free set, p.g, max |p|
+        phase_break();
         double v[2] = {0.0, 0.0};
         double pm = 0.0;
 #pragma unroll
@@ -634,7 +660,7 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             if (spend && f) pv[k] += carry[k] * pendc;
             const double pi = f ? -pv[k] : 0.0;
             pv[k] = pi;
-            v[0] += pi * g[k];
+            v[0] += pi * (in(k) ? *at(gg, k) : 0.0);
             v[1] += isfinite(pi) ? 0.0 : 1.0;
             pm = fmax(pm, fabs(pi));
         }
@@ -646,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             pm = 0.0;
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                pv[k] = ((fr >> k) & 1u) ? -g[k] : 0.0;
+                pv[k] = ((fr >> k) & 1u) ? -*at(gg, k) : 0.0;
                 pm = fmax(pm, fabs(pv[k]));
             }
         }
@@ -657,21 +683,25 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
     }
 
     if (!finish && s.state != ST_DONE) {
+        if (!need_dir) {  // a backtracking step keeps its direction
+#pragma unroll
+            for (int k = 0; k < PT; ++k) pv[k] = in(k) ? *at(pgl, k) : 0.0;
+        }
         // trial point y(alpha) = clip(y + alpha p, 0, 1) and the Armijo reference g.(yt - y); a
         // clamped step that does not descend restarts the search along -Pg (as in k_opt_update)
         for (;;) {
+            phase_break();
             double v[1] = {0.0};
 #pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
-                if (i < K) {
-                    double t = y[k] + s.alpha * pv[k];
+            for (int k = 0; k < PT; ++k)
+                if (in(k)) {
+                    const double yk = *at(yg, k);
+                    double t = yk + s.alpha * pv[k];
                     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-                    ytg[i] = t;
-                    xtg[i] = lo[i] + t * (hi[i] - lo[i]);
-                    v[0] += g[k] * (t - y[k]);
+                    *at(ytg, k) = t;
+                    *at(xtg, k) = *at(lo, k) + t * (*at(hi, k) - *at(lo, k));
+                    v[0] += *at(gg, k) * (t - yk);
                 }
-            }
             block_sum<1, NT>(v, red);
             s.dec = v[0];
             if (s.dec < 0.0 || s.sd) break;
@@ -679,11 +709,13 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
             s.newest = -1;
             s.sd = 1;
             s.nbt = 0;
+            pv_new = true;
             double pm = 0.0;
+            phase_break();
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                const int64_t i = (int64_t)k * NT + tid;
-                pv[k] = (i < K && is_free(y[k], g[k])) ? -g[k] : 0.0;
+                const double gk = in(k) ? *at(gg, k) : 0.0;
+                pv[k] = (in(k) && is_free(*at(yg, k), gk)) ? -gk : 0.0;
                 pm = fmax(pm, fabs(pv[k]));
             }
             pm = block_max<NT>(pm, red[0]);
@@ -691,14 +723,10 @@ __global__ __launch_bounds__(NT) void k_opt_update_tile(OptArgs a) {
         }
         s.state = ST_SEARCH;
     }
+    if (pv_new) {
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const int64_t i = (int64_t)k * NT + tid;
-        if (i < K) {
-            yg[i] = y[k];
-            gg[i] = g[k];
-            pgl[i] = pv[k];
-        }
+        for (int k = 0; k < PT; ++k)
+            if (in(k)) *at(pgl, k) = pv[k];
     }
     if (finish) {
         s.status |= finish;
@@ -763,7 +791,7 @@ __device__ __forceinline__ void block_best(double &v, int64_t &idx, double *shv,
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ada_update(OptArgs a) {
     const int item = blockIdx.x;
-    if (!a.active[item]) return;
+    if (!as_const(a.active)[item]) return;
     __shared__ double red[8][16];
     __shared__ double bv[16];
     __shared__ int64_t bi[16];
@@ -773,10 +801,10 @@ __global__ __launch_bounds__(NT) void k_ada_update(OptArgs a) {
     double *y = a.y + o, *g = a.g + o, *d = a.p + o, *yt = a.yt + o, *xt = a.xt + o;
     double *mm = a.S + o, *vv = a.T + o;
     int32_t *piv = a.piv + o;
-    OptItem s = a.st[item];  // every thread holds the same copy
+    OptItem s = load_uniform(a.st + item);  // every thread holds the same copy, in scalar registers
     s.nevals += 1;
-    const double fe = a.fe[item];
-    const int32_t est = a.estat[item];
+    const double fe = as_const(a.fe)[item];
+    const int32_t est = as_const(a.estat)[item];
     const bool evalok = !(est & (CS_ITEM_NOT_PD | CS_ITEM_NONFINITE)) && isfinite(fe);
     int32_t finish = 0;
     bool iterate = false;  // start a new iteration from the current point
@@ -1184,6 +1212,8 @@ cs_status optimize(cs_problem *p, const cs_optim_opts *o, const double *lo, cons
                         hipLaunchKernelGGL(k_ada_update<1024>, dim3(B), dim3(1024), 0, s, a);
                     else if (kmax <= 64 * 8)
                         hipLaunchKernelGGL((k_opt_update_tile<64, 8>), dim3(B), dim3(64), 0, s, a);
+                    else if (kmax <= 512 * 15)  // fits its registers without spilling
+                        hipLaunchKernelGGL((k_opt_update_tile<512, 15>), dim3(B), dim3(512), 0, s, a);
                     else if (kmax <= 512 * 16)
                         hipLaunchKernelGGL((k_opt_update_tile<512, 16>), dim3(B), dim3(512), 0, s, a);
                     else

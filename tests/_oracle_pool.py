@@ -34,6 +34,14 @@ def _lbfgs(args):
     return x, f, it, ne, st
 
 
+def _eval(args):
+    """F, gradient, cluster values and status of one item at x, with the per-cluster rounding
+    scale of its gradient terms."""
+    freqs, d, ninv, labels, ncl, nu0d, nu0s, tcmb, x = args
+    pr = oracle.Problem(freqs, d, ninv, labels, ncl, nu0d, nu0s, tcmb)
+    return pr.likelihood_grad(x), pr.grad_terms(x)
+
+
 def _scan_item(args):
     """One configuration of the scan: its three patchings by the oracle's K-means, then the
     oracle's L-BFGS from x0 on those labels; returns (labels [3][P], keff [3], x, F, iters, status)."""
@@ -60,6 +68,10 @@ def run(fn, jobs):
 
 def lbfgs_many(jobs):
     return run(_lbfgs, jobs)
+
+
+def eval_many(jobs):
+    return run(_eval, jobs)
 
 
 def scan_many(jobs):

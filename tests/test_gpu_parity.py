@@ -8,6 +8,7 @@ import torch
 
 import skygen
 from oracle import oracle
+from tests import _oracle_pool as pool
 from tests._parity import TOL_F, check_grad, compare, gpu_eval
 
 pytestmark = pytest.mark.gpu
@@ -431,13 +432,18 @@ def test_fp32_bulk_optimum_within_1e4_reduced_workload5():
 
 def test_workload5_full_size_sampled_items():
     # the benchmark's workload at full size and in its launch configuration (autotuned schedule):
-    # every item evaluated on the device, two sampled items recomputed by the oracle
+    # every item evaluated on the device, eight items spread over the batch recomputed by the
+    # oracle (in parallel worker processes)
     sky = skygen.make_config(5, device="cuda")
     x = torch.as_tensor(sky.x_packed(), device="cuda")
     off = sky.param_offsets()
-    picks = (0, 37)
-    ref = {b: oracle.Problem.from_sky(sky, b).likelihood_grad(sky.x[b]) for b in picks}
-    terms = {b: oracle.Problem.from_sky(sky, b).grad_terms(sky.x[b]) for b in picks}
+    picks = (0, 9, 18, 27, 37, 46, 55, 63)
+    jobs = [(sky.freqs, sky.item_d(b), sky.ninv, sky.item_labels(b), sky.nclusters[b], sky.nu0_dust, sky.nu0_sync,
+             sky.tcmb, sky.x[b]) for b in picks]
+    out = pool.eval_many(jobs)
+    ref = {b: o[0] for b, o in zip(picks, out)}
+    terms = {b: o[1] for b, o in zip(picks, out)}
+    del jobs
     for precision, tf in (("fp32_bulk", 1e-5), ("fp64", 1e-12)):
         prob = cs.Problem.from_sky(sky, precision)
         s = prob.autotune(x, reps=1)

@@ -217,31 +217,49 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
 
 // a7 (first level): inclusive scan inside each constant-label run of the wavefront; the run's
 // last lane holds the run total and writes the segment's (f, dF/dbeta_d, dF/dT_d, dF/dbeta_s).
-// Run-segmented sums of the wavefront's per-pixel values; the last lane of each segment writes
-// the segment's (f, dF/dbeta_d, dF/dT_d, dF/dbeta_s).  A non-finite gradient partial sets the
-// item's NONFINITE bit here (every lane of the wavefront must be active).
+// The scan moves values between lanes by DPP (VALU only, no LDS round trip): within each 16-lane
+// row it adds the lane 1, 2, 4 and 8 places below when that lane is in the same run, then each
+// odd row adds the last lane of the row below and rows 2 and 3 add lane 31, each again only when
+// the source lane is in the same run.  A non-finite gradient partial sets the item's NONFINITE
+// bit here (every lane of the wavefront must be active).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_from(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <bool GRAD, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_step(bool take, double &f, double &g1, double &g2, double &g3) {
+    const double of = dpp_from<CTRL, ROW_MASK>(f);
+    double o1 = 0, o2 = 0, o3 = 0;
+    if (GRAD) {
+        o1 = dpp_from<CTRL, ROW_MASK>(g1);
+        o2 = dpp_from<CTRL, ROW_MASK>(g2);
+        o3 = dpp_from<CTRL, ROW_MASK>(g3);
+    }
+    if (take) {
+        f += of;
+        if (GRAD) {
+            g1 += o1;
+            g2 += o2;
+            g3 += o3;
+        }
+    }
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 template <bool GRAD>
 __device__ __forceinline__ void seg_reduce_write(uint64_t head, int lane, double fpix, double g1, double g2,
                                                  double g3, double *out, int32_t *status) {
     const int start = 63 - __clzll(head & lanemask_le(lane));
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double of = __shfl_up(fpix, off, 64);
-        double o1 = 0, o2 = 0, o3 = 0;
-        if (GRAD) {
-            o1 = __shfl_up(g1, off, 64);
-            o2 = __shfl_up(g2, off, 64);
-            o3 = __shfl_up(g3, off, 64);
-        }
-        if (lane - off >= start) {
-            fpix += of;
-            if (GRAD) {
-                g1 += o1;
-                g2 += o2;
-                g3 += o3;
-            }
-        }
-    }
+    const int r16 = lane & 15;
+    seg_step<GRAD, kDppRowShr1, 0xf>(r16 >= 1 && lane - 1 >= start, fpix, g1, g2, g3);
+    seg_step<GRAD, kDppRowShr2, 0xf>(r16 >= 2 && lane - 2 >= start, fpix, g1, g2, g3);
+    seg_step<GRAD, kDppRowShr4, 0xf>(r16 >= 4 && lane - 4 >= start, fpix, g1, g2, g3);
+    seg_step<GRAD, kDppRowShr8, 0xf>(r16 >= 8 && lane - 8 >= start, fpix, g1, g2, g3);
+    seg_step<GRAD, kDppRowBcast15, 0xa>(((lane >> 4) & 1) && (lane & ~15) - 1 >= start, fpix, g1, g2, g3);
+    seg_step<GRAD, kDppRowBcast31, 0xc>(lane >= 32 && 31 >= start, fpix, g1, g2, g3);
     const bool last = (lane == 63) || ((head >> (lane + 1)) & 1ull);
     if (last) {
         out[0] = fpix;

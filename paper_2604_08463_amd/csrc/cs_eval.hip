@@ -222,10 +222,12 @@ __device__ __forceinline__ void band_loop(const int F, const gptr<TS> dq, const 
 // odd row adds the last lane of the row below and rows 2 and 3 add lane 31, each again only when
 // the source lane is in the same run.  A non-finite gradient partial sets the item's NONFINITE
 // bit here (every lane of the wavefront must be active).
+// The moved value is undefined in lanes the pattern does not reach (rows outside ROW_MASK, sources
+// outside the row); seg_step never adds it there.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_from(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, ROW_MASK, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 template <bool GRAD, int CTRL, int ROW_MASK>

@@ -37,6 +37,26 @@ __device__ __forceinline__ T ld_stream(gptr<T> p) {
 #endif
 }
 
+// Streamed load through a raw buffer descriptor: voffset (per lane) + soffset (uniform) bytes,
+// nontemporal like ld_stream.  kRawBufferDword3 is the descriptor's fourth dword for raw 32-bit
+// data on this ISA (data format field = 32 bit, no swizzle or stride).
+constexpr int kRawBufferDword3 = 0x00020000;
+#if CS_NT_LOADS
+constexpr int kBufAux = 2;  // nt
+#else
+constexpr int kBufAux = 0;
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_stream_buf(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kBufAux));
+    } else {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kBufAux);
+        return __longlong_as_double((long long)(((uint64_t)v.y << 32) | v.x));
+    }
+}
+
 __device__ __forceinline__ uint64_t lanemask_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }

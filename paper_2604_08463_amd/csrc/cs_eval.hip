@@ -546,9 +546,14 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
     const bool valid = lane < nvalid;
     const int segl = __popcll(head & lanemask_le(lane)) - 1;
     const int64_t kd = it->k[0], kt = it->k[1];
-    const int64_t cbase = (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk) + lane;
-    const gptr<TS> dq = as_global((const TS *)a.dpack) + cbase;
-    const gptr<TS> du = dq + (int64_t)F * kChunk;
+    // the chunk's data through a buffer descriptor: the band's byte offset in a scalar register,
+    // the lane's in one vector register shared by every band, so a load needs no per-lane address
+    // arithmetic (and the descriptor's range bounds every access to the chunk)
+    const TS *dchunk = (const TS *)a.dpack + (it->dchunk0 + chunk) * (2 * (int64_t)F * kChunk);
+    const __amdgpu_buffer_rsrc_t drsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)dchunk, (short)0, (int)(2 * F * kChunk * (int)sizeof(TS)), kRawBufferDword3);
+    const int lane_bytes = lane * (int)sizeof(TS);
+    auto ld_band = [&](int s, int f) { return ld_stream_buf<TS>(drsrc, lane_bytes, (s * F + f) * kChunk * (int)sizeof(TS)); };
 
     // data ring: groups 0 .. kRing-1, requested before anything else, except on the FP32
     // per-pixel fast path below, which sends it behind its table gathers
@@ -560,8 +565,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
             for (int j = 0; j < kG; ++j) {
                 const int f0 = r * kG + j;
                 const int f = f0 < F ? f0 : F - 1;
-                rq[r][j] = ld_stream(dq + f * kChunk);
-                ru[r][j] = ld_stream(du + f * kChunk);
+                rq[r][j] = ld_band(0, f);
+                ru[r][j] = ld_band(1, f);
             }
     };
     // table offsets of the fast path are 32-bit byte offsets
@@ -884,8 +889,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
                 for (int j = 0; j < kG; ++j) {
                     const int f0 = fb + kRing * kG + j;
                     const int f = f0 < F ? f0 : F - 1;
-                    rq[r][j] = ld_stream(dq + f * kChunk);
-                    ru[r][j] = ld_stream(du + f * kChunk);
+                    rq[r][j] = ld_band(0, f);
+                    ru[r][j] = ld_band(1, f);
                 }
             }
         }

@@ -113,6 +113,8 @@ static void fill_band(const cs_problem *p, BandDev &b) {
         }
         b.wsum[s] = t;
         b.wsumf[s] = tf;
+        b.isw[s] = 1.0 / std::sqrt(t);
+        b.iswf[s] = 1.0 / std::sqrt((double)(float)t);
     }
 }
 

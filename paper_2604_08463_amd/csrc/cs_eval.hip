@@ -52,6 +52,7 @@ struct Band<double> {
     static __device__ __forceinline__ double ld(cptr<BandDev> b, int f) { return b->ld[f]; }
     static __device__ __forceinline__ double ls(cptr<BandDev> b, int f) { return b->ls[f]; }
     static __device__ __forceinline__ double wsum(cptr<BandDev> b, int s) { return b->wsum[s]; }
+    static __device__ __forceinline__ double isw(cptr<BandDev> b, int s) { return b->isw[s]; }
 };
 template <>
 struct Band<float> {
@@ -59,6 +60,7 @@ struct Band<float> {
     static __device__ __forceinline__ float ld(cptr<BandDev> b, int f) { return b->ldf[f]; }
     static __device__ __forceinline__ float ls(cptr<BandDev> b, int f) { return b->lsf[f]; }
     static __device__ __forceinline__ float wsum(cptr<BandDev> b, int s) { return b->wsum[s]; }
+    static __device__ __forceinline__ double isw(cptr<BandDev> b, int s) { return b->iswf[s]; }
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -109,6 +111,22 @@ __global__ __launch_bounds__(kSedThreads) void k_sed(const EvalArgs a, const int
 // principal minors m00, m00 p1 and m00 p1 p2 must be positive relative to the products of their
 // diagonal entries (p1 / m11 and p1 p2 / (m11 m22) above a tolerance of the accumulation
 // precision), so that a rank-deficient M is flagged whatever sign rounding gives its last pivot.
+// 1 / sqrt(p) of a Cholesky pivot.  FP64 accumulation: correctly rounded.  FP32 accumulation,
+// whose M already carries FP32 rounding: the hardware reciprocal square root (relative error
+// below 2^-22) refined by one Newton step to a relative error of about 1e-13, at a quarter of
+// the instructions of a rounded square root and division.  A pivot that is zero, negative or
+// not finite gives inf or NaN either way and fails the positive-definiteness test.
+template <typename TA>
+__device__ __forceinline__ double inv_sqrt(double p) {
+    if constexpr (sizeof(TA) == 8) {
+        return 1.0 / sqrt(p);
+    } else {
+        const double y = __builtin_amdgcn_rsq(p);
+        const double r = fma(-p * y, y, 1.0);  // 1 - p y^2
+        return fma(0.5 * y, r, y);
+    }
+}
+
 template <typename TA>
 __device__ __forceinline__ bool pd_pivots(double m00, double m11, double m22, double p1, double p2) {
     constexpr double kTau = sizeof(TA) == 4 ? 1e-6 : 1e-12;
@@ -378,16 +396,13 @@ __device__ __forceinline__ void unit_pixel(const EvalArgs &a, const int item, co
             const WAcc<TA> &c = A[n];
             const double m00 = (WM == 2) ? (double)c.m00 : (double)Band<TA>::wsum(B, n);
             const double m01 = c.m01, m02 = c.m02, m11 = c.m11, m12 = c.m12, m22 = c.m22;
-            const double l00 = sqrt(m00);
-            const double i00 = 1.0 / l00;
+            const double i00 = (WM == 2) ? inv_sqrt<TA>(m00) : Band<TA>::isw(B, n);
             const double l10 = m01 * i00, l20 = m02 * i00;
             const double p1 = m11 - l10 * l10;
-            const double l11 = sqrt(p1);
-            const double i11 = 1.0 / l11;
+            const double i11 = inv_sqrt<TA>(p1);
             const double l21 = (m12 - l20 * l10) * i11;
             const double p2 = m22 - l20 * l20 - l21 * l21;
-            const double l22 = sqrt(p2);
-            const double i22 = 1.0 / l22;
+            const double i22 = inv_sqrt<TA>(p2);
             ok = ok && pd_pivots<TA>(m00, m11, m22, p1, p2);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -764,13 +779,13 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         if (part == 0 && sg < nseg) {
             const double m00 = (double)Band<TA>::wsum(B, 0);
             const double m01 = P.m01, m02 = P.m02, m11 = P.m11, m12 = P.m12, m22 = P.m22;
-            const double i00 = 1.0 / sqrt(m00);
+            const double i00 = Band<TA>::isw(B, 0);
             const double l10 = m01 * i00, l20 = m02 * i00;
             const double p1 = m11 - l10 * l10;
-            const double i11 = 1.0 / sqrt(p1);
+            const double i11 = inv_sqrt<TA>(p1);
             const double l21 = (m12 - l20 * l10) * i11;
             const double p2 = m22 - l20 * l20 - l21 * l21;
-            const double i22 = 1.0 / sqrt(p2);
+            const double i22 = inv_sqrt<TA>(p2);
             double *r = recs + sg;
             r[kI00 * kStageSeg] = i00;
             r[kL10 * kStageSeg] = l10;
@@ -931,14 +946,14 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         }
         const double m00 = (double)Band<TA>::wsum(B, 0);
         const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;
-        i00 = 1.0 / sqrt(m00);
+        i00 = Band<TA>::isw(B, 0);
         l10 = m01 * i00;
         l20 = m02 * i00;
         const double p1 = m11 - l10 * l10;
-        i11 = 1.0 / sqrt(p1);
+        i11 = inv_sqrt<TA>(p1);
         l21 = (m12 - l20 * l10) * i11;
         const double p2 = m22 - l20 * l20 - l21 * l21;
-        i22 = 1.0 / sqrt(p2);
+        i22 = inv_sqrt<TA>(p2);
         ok = pd_pivots<TA>(m00, m11, m22, p1, p2);
         G[0] = A.g01; G[1] = A.g02; G[2] = A.g03;
         G[3] = A.g11; G[4] = A.g12; G[5] = A.g13;

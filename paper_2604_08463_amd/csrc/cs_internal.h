@@ -35,6 +35,8 @@ struct BandDev {
     float wsumf[2];
     float bcf[kFMax][4];   // (w[0][f], ld[f], ls[f], 0) packed, FP32 copies
     double bcd[kFMax][4];  // the same in FP64
+    double isw[2];         // 1 / sqrt(wsum[s]): the first Cholesky pivot's inverse
+    double iswf[2];        // the same of wsum[s] rounded to FP32 (the FP32-accumulation m00)
 };
 
 // One label layout: the labelling of one item, or the labelling shared by every item.

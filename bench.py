@@ -95,7 +95,8 @@ def _roctx():
 def measured_traffic(schedule):
     """HBM bytes per launch of the pixel kernel from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE scaled by a plain copy's readings), or None unless that summary was taken on the
-    current kernel source and the same schedule mode."""
+    current kernel source with the same grid form, XCD mapping and schedule mode (these decide
+    which L2 fetches which SED table)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -103,10 +104,14 @@ def measured_traffic(schedule):
             src = hashlib.sha256(fh.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    mode = int(schedule.get("shared_segments", 0)) if schedule else 0
-    if rec.get("kernel_source_sha256") != src or rec.get("shared_segments") != mode:
+    if not schedule or rec.get("kernel_source_sha256") != src:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    key = tuple(int(schedule.get(k, 0)) for k in ("blocks_per_cu", "xcd_remap", "shared_segments"))
+    for r in rec.get("records", []):
+        s = [int(v) for v in r["counter_schedule"].split(",")]
+        if (s[1], s[2], s[3]) == key:
+            return r["traffic_bytes_per_launch"]
+    return None
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

@@ -448,8 +448,9 @@ def test_workload5_full_size_sampled_items():
     for precision, tf in (("fp32_bulk", 1e-5), ("fp64", 1e-12)):
         prob = cs.Problem.from_sky(sky, precision)
         s = prob.autotune(x, reps=1)
-        # the autotuned schedule, then each staging mode by hand (FP32: per-pixel and segment sums)
-        scheds = [None] + ([(2, 0, 0, 0), (2, 0, 0, 2)] if precision == "fp32_bulk" else [])
+        # the autotuned schedule, then each staging mode by hand (FP32: per-pixel and segment sums),
+        # and one wavefront per workgroup with each XCD on a contiguous range of items
+        scheds = [None] + ([(2, 0, 0, 0), (2, 0, 0, 2), (1, 0, 1, 2)] if precision == "fp32_bulk" else [(1, 0, 1, 0)])
         for sc in scheds:
             if sc is not None:
                 prob.set_schedule(*sc)

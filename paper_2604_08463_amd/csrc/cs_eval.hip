@@ -609,6 +609,8 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const int rb = F * (int)sizeof(TA);  // bytes per table row
         const int kdb = (int)kd * rb, kdtb = (int)(kd + 2 * kt) * rb;
         const bool hi = lane >= 32;
+        int hmask = hi ? -1 : 0;  // selects the second half's offset differences
+        asm volatile("" : "+v"(hmask));  // kept as a mask: one AND per offset, not a select
         int f = lane & 31;
         // segment-sum mode: the staging's LDS addresses are formed per unit (hoisted out of the
         // unit loop they would hold 18 registers through the band loop)
@@ -637,9 +639,9 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
                     ds = two ? kdtb + l1[2] * rb - bs : 0;
                 // keep the products on the scalar unit (not re-formed per lane after the select)
                 asm volatile("" : "+s"(bd), "+s"(bt2), "+s"(bs), "+s"(dd), "+s"(dt2), "+s"(ds));
-                const int ed = bd + (hi ? dd : 0) + fb;
-                const int et = bt2 + (hi ? dt2 : 0) + 2 * fb;
-                const int es = bs + (hi ? ds : 0) + fb;
+                const int ed = bd + (dd & hmask) + fb;
+                const int et = bt2 + (dt2 & hmask) + 2 * fb;
+                const int es = bs + (ds & hmask) + fb;
                 pdv[r] = at(ed);
                 btv[r] = at(et);
                 dtv[r] = at(et + (int)sizeof(TA));
@@ -820,14 +822,23 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         const TA *up = im < 4 ? &cols[sgm * F].x + im : c5 + sgm * F;
         const int ust = im < 4 ? 4 : 1;
         const Vec2<TA> *vp = v2 + sgm * F;
-#pragma unroll 2
-        for (int f = 0; f < F; ++f) {
-            const TA u = *up;
-            up += ust;
-            const Vec2<TA> v = vp[f];
+        auto add = [&](const TA u, const Vec2<TA> v) {
             ms0 += u;
             ms1 = fma(u, v.x, ms1);
             ms2 = fma(u, v.y, ms2);
+        };
+        int f = 0;
+        for (; f + 4 <= F; f += 4) {  // four bands per step: one pointer step, v2 by immediate offsets
+            const TA u0 = up[0], u1 = up[ust], u2 = up[2 * ust], u3 = up[3 * ust];
+            up += 4 * ust;
+            add(u0, vp[f]);
+            add(u1, vp[f + 1]);
+            add(u2, vp[f + 2]);
+            add(u3, vp[f + 3]);
+        }
+        for (; f < F; ++f) {
+            add(*up, vp[f]);
+            up += ust;
         }
     }
 
@@ -927,22 +938,25 @@ __device__ __forceinline__ void unit_staged(const EvalArgs &a, const int item, c
         G[6] = R[kG21 * kStageSeg]; G[7] = R[kG22 * kStageSeg]; G[8] = R[kG23 * kStageSeg];
         ok = R[kOk * kStageSeg] != 0.0;
     } else {
-        if (SUMS) {  // the segment's sums from its five lanes
-            const int src = 5 * segl;
-            A.m01 = __shfl(ms0, src);
-            A.m11 = __shfl(ms1, src);
-            A.m12 = __shfl(ms2, src);
-            A.m02 = __shfl(ms0, src + 1);
-            A.m22 = __shfl(ms2, src + 1);
-            A.g01 = __shfl(ms0, src + 2);
-            A.g11 = __shfl(ms1, src + 2);
-            A.g21 = __shfl(ms2, src + 2);
-            A.g02 = __shfl(ms0, src + 3);
-            A.g12 = __shfl(ms1, src + 3);
-            A.g22 = __shfl(ms2, src + 3);
-            A.g03 = __shfl(ms0, src + 4);
-            A.g13 = __shfl(ms1, src + 4);
-            A.g23 = __shfl(ms2, src + 4);
+        if (SUMS) {  // the segment's sums from its five lanes (lanes 5 segl + i <= 59)
+            const int src = 20 * segl;  // byte address of lane 5 segl
+            auto from = [&](TA v, int i) {
+                return __int_as_float(__builtin_amdgcn_ds_bpermute(src + 4 * i, __float_as_int(v)));
+            };
+            A.m01 = from(ms0, 0);
+            A.m11 = from(ms1, 0);
+            A.m12 = from(ms2, 0);
+            A.m02 = from(ms0, 1);
+            A.m22 = from(ms2, 1);
+            A.g01 = from(ms0, 2);
+            A.g11 = from(ms1, 2);
+            A.g21 = from(ms2, 2);
+            A.g02 = from(ms0, 3);
+            A.g12 = from(ms1, 3);
+            A.g22 = from(ms2, 3);
+            A.g03 = from(ms0, 4);
+            A.g13 = from(ms1, 4);
+            A.g23 = from(ms2, 4);
         }
         const double m00 = (double)Band<TA>::wsum(B, 0);
         const double m01 = A.m01, m02 = A.m02, m11 = A.m11, m12 = A.m12, m22 = A.m22;
